@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Benchmark of the bias-force hot path on one MI355X.
+
+Headline: bias evaluations per second (walker-steps/s) of the direct hill
+sum in FP32 with Kahan compensation, on the 2-D torsion workload (50,000
+hills, heights 1.2 exp(-k/20000), sigma 0.3; 1,048,576 queries = 1024
+walkers x 1024 steps), inputs resident in HBM. One step = one bias_eval over
+all queries. Printed as one JSON line, with the FP64 direct sum, the plain
+FP32 sum, the grid path, the fused bias-force path and (when built) the
+serving loop's latency as secondary figures, the roofline of the direct-sum
+kernel, and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the figures derived from unit counts.
+CU, LANES, CLOCK = 256, 64, 2.4e9
+FP32_VECTOR_PEAK_TFLOPS = 157.3        # published: packed FMA on every lane every clock
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+VALU_LANE_OPS = CU * LANES * CLOCK     # non-packed VALU issue: 3.93e13 lane-ops/s
+# Algorithmic flops per (query, hill) pair of the 2-D periodic Gaussian sum:
+# per axis: difference 1, minimum image 2, scale 1, square-accumulate 2,
+# gradient FMA 2; plus height multiply 1 and value add 1; the exp is not counted.
+FLOPS_PER_PAIR_2D = 18
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(spec, hills, q, target_s=15.0):
+    """The FP64 oracle on an evenly spaced sample of the queries, all host cores."""
+    import numpy as np
+    import oracle
+    nq = q.shape[1]
+    probe = 64
+    idx = np.linspace(0, nq - 1, probe).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.hill_sum(spec, hills.centers, hills.heights, q[:, idx])
+    dt = time.perf_counter() - t0
+    n = int(min(nq, max(probe, probe * target_s / max(dt, 1e-6))))
+    idx = np.linspace(0, nq - 1, n).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.hill_sum(spec, hills.centers, hills.heights, q[:, idx])
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} of {nq} queries (evenly spaced) against all {hills.n} hills, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU form "
+              "in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1609_09833_amd import abp
+    from paper_1609_09833_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    log("bench: generating the 2-D torsion workload (50,000 hills, 1,048,576 queries)")
+    spec, hills, q = W.torsion_2d()
+    nq, nh = q.shape[1], hills.n
+    ctx = abp.Context(spec, capacity=nh)
+    cen_d = torch.as_tensor(hills.centers, device=dev)
+    hts_d = torch.as_tensor(hills.heights, device=dev)
+    t0 = time.perf_counter()
+    abp.bias_deposit(ctx, cen_d, hts_d)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    qd = torch.as_tensor(q, device=dev)
+    V = torch.empty(nq, dtype=torch.float32, device=dev)
+    dV = torch.empty((2, nq), dtype=torch.float32, device=dev)
+
+    def step_kahan():
+        abp.bias_eval(ctx, qd, prec=abp.ABP_PREC_FP32_KAHAN, V=V, dVds=dV)
+
+    log(f"bench: headline FP32-Kahan direct sum, {args.warmup} warmup + {args.steps} timed steps")
+    el, wall = timed(step_kahan, args.steps, args.warmup, stream)
+    abp.abp_sync(ctx)
+    ms_step = el / args.steps * 1e3
+    value = nq * args.steps / el
+    pairs_s = value * nh
+    achieved_tflops = pairs_s * FLOPS_PER_PAIR_2D / 1e12
+    out = {
+        "metric": "bias-force evals/sec (walker-steps) at 50k hills, FP32 vs FP64 plain; p99 latency",
+        "value": value,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D periodic torsion CV space, direct hill sum, FP32 + Kahan, plain bias",
+                   "hills": nh, "queries_per_step": nq, "walkers": 1024, "steps_per_walker": 1024,
+                   "sigma": [0.3, 0.3], "heights": "1.2*exp(-k/20000)", "query_io": "f32"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_direct_f32<2,3,GAUSS,2>", "pairs_per_s": pairs_s,
+                     "kernel_ms": ms_step},
+    }
+    log(f"bench: headline {value:.4e} walker-steps/s ({ms_step:.3f} ms/step, {pairs_s:.3e} pairs/s)")
+    if args.only_headline:
+        print(json.dumps(out), flush=True)
+        return
+
+    extra = {}
+    for name, prec, steps in (("fp64_direct", abp.ABP_PREC_FP64, max(2, args.steps // 4)),
+                              ("fp32_naive_direct", abp.ABP_PREC_FP32_NAIVE, args.steps)):
+        def fn(prec=prec):
+            abp.bias_eval(ctx, qd, prec=prec, V=V, dVds=dV)
+        el2, _ = timed(fn, steps, 1, stream)
+        extra[name] = {"walker_steps_per_s": nq * steps / el2, "ms_per_step": el2 / steps * 1e3}
+        log(f"bench: {name} {nq * steps / el2:.4e} walker-steps/s")
+    # grid: accumulate 50,000 hills into a 256^2 FP64 grid, then interpolate at all queries
+    gctx = abp.Context(spec, capacity=nh)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    abp.bias_deposit(gctx, cen_d, hts_d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    extra["grid_build_ms"] = e0.elapsed_time(e1)
+    del build_s
+
+    def grid_step():
+        abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
+    el3, _ = timed(grid_step, args.steps, 2, stream)
+    extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
+                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
+    log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
+    # fused bias-force: 1024 walkers of 2,000-8,000 atoms, COM distance + torsion, 20,000 hills
+    wk = W.ligand_pocket_walkers()
+    fspec, fhills = W.ligand_pocket_hills()
+    fctx = abp.Context(fspec, capacity=fhills.n)
+    abp.bias_deposit(fctx, torch.as_tensor(fhills.centers, device=dev), torch.as_tensor(fhills.heights, device=dev))
+    dw = abp.DeviceWalkers(wk, device=dev)
+    s_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
+    V_o = torch.empty(wk.nw, dtype=torch.float64, device=dev)
+    dV_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
+    for mode, name in ((abp.ABP_EVAL_DIRECT, "bias_force_direct"), (abp.ABP_EVAL_GRID, "bias_force_grid")):
+        def fstep(mode=mode):
+            abp.bias_force(fctx, dw, mode=mode, s=s_o, V=V_o, dVds=dV_o)
+        el4, _ = timed(fstep, args.steps, 2, stream)
+        extra[name] = {"walker_steps_per_s": wk.nw * args.steps / el4, "ms_per_step": el4 / args.steps * 1e3,
+                       "walkers": wk.nw, "hills": fhills.n}
+        log(f"bench: {name} {wk.nw * args.steps / el4:.4e} walker-steps/s")
+    abp.abp_sync(fctx)
+    out["extra"] = extra
+    out["valu_issue"] = {"lane_ops_per_s_peak": VALU_LANE_OPS,
+                         "note": "non-packed VALU issue rate; see DESIGN.md for the per-pair instruction count"}
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(spec, hills, q)
+        log(f"bench: oracle {out['cpu_baseline']['value']:.4e} walker-steps/s on {out['cpu_baseline']['cores']} cores")
+    del np
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/* abp.h - C-ABI of libabp.so, the GPU (AMD gfx950) library for the bias-force
+ * hot path of adaptive biasing potentials with compact or Gaussian hills.
+ *
+ * Method: Dickson, de Waal, Ramjan, Xu, Rothbart, "A fast, open source
+ * implementation of adaptive biasing potentials uncovers a ligand design
+ * strategy for the chromatin regulator BRD4", arXiv:1609.09833. Equation
+ * names below refer to its Supplemental Material, section "Streamlined bias
+ * potential updates" (eqs. apfm, btraj-grad, histos, ghill, update,
+ * compacthill, Cupdate), section "Convergence with S_a^p" (width relations)
+ * and section "Definition of the RMSD".
+ *
+ * The problem the calls solve is the one the paper's engine hands to its bias
+ * routine every MD step (section "Minimization of Interprocess
+ * Communications"): given the coordinates of the atoms that enter the
+ * collective variables (CVs), update the bias from the visited CV value and
+ * return the bias force on exactly those atoms, which the engine adds to its
+ * own forces.
+ *
+ * Conventions shared by every call
+ * - Array arguments are DEVICE pointers owned by the caller, unless a comment
+ *   says "host". The library never frees them and never uses them after the
+ *   work it enqueued on `stream` has run.
+ * - CV-space arrays are dimension-major: x[i*n + j] is coordinate i of item j.
+ * - All compute calls are asynchronous on `stream` (a hipStream_t; NULL means
+ *   the null stream). Errors that the host can see (bad descriptors, NULL
+ *   pointers, negative sizes, capacity) are returned synchronously before
+ *   anything is enqueued, and then nothing is enqueued.
+ * - Errors only the device can see (atom index out of range, non-finite
+ *   input, a negative hill height) set a per-context device error word; the
+ *   affected walker or item is skipped and the rest completes. abp_sync()
+ *   returns that error and clears the word.
+ * - A context is not thread-safe: use one host thread per context, or lock.
+ * - On error, abp_last_error() returns a message for the calling thread.
+ */
+#ifndef ABP_H
+#define ABP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abp_ctx abp_ctx;   /* opaque: owns the hill history, grids, workspace */
+typedef void* abp_stream;         /* a hipStream_t */
+
+typedef enum {
+  ABP_OK = 0,
+  ABP_E_INVAL = 1,       /* bad argument or descriptor */
+  ABP_E_NOMEM = 2,       /* device allocation failed */
+  ABP_E_CAPACITY = 3,    /* the history would exceed its capacity */
+  ABP_E_DEVICE = 4,      /* a HIP runtime call failed */
+  ABP_E_INDEX = 5,       /* device-detected: atom index out of range or list not valid */
+  ABP_E_NONFINITE = 6    /* device-detected: non-finite position/mass/height, or negative height */
+} abp_status;
+
+typedef enum { ABP_F32 = 0, ABP_F64 = 1 } abp_dtype;
+
+/* Arithmetic of the hill sum (see bias_eval). */
+typedef enum {
+  ABP_PREC_FP32_KAHAN = 0,  /* FP32 terms, compensated (Kahan) accumulation */
+  ABP_PREC_FP32_NAIVE = 1,  /* FP32 terms, plain FP32 accumulation */
+  ABP_PREC_FP64 = 2         /* FP64 throughout */
+} abp_prec;
+
+/* Hill shape per CV axis; the multi-dimensional hill is the product over axes
+ * (eq. ghill is already such a product; eq. compacthill and the sentence after
+ * it define the product for the compact kernel). */
+typedef enum {
+  ABP_K_GAUSS = 0,    /* exp(-delta^2/(2 sigma^2)): eq. ghill with alpha = sqrt(2) sigma */
+  ABP_K_COMPACT = 1   /* S_a^p(delta) = e^p exp(-p/(1-(delta/a)^2)) for |delta/a| < 1, else 0 (eq. compacthill) */
+} abp_kernel;
+
+typedef enum {
+  ABP_T_PLAIN = 0,    /* V = h (the accumulated hill sum) */
+  ABP_T_MABP = 1      /* V = kT b/(1-b) ln(c(1-b) h + 1), eq. apfm; gradient eq. btraj-grad */
+} abp_transform;
+
+typedef enum {
+  ABP_EVAL_DIRECT = 0,  /* sum over the deposited hills (eq. histos with the integral over time
+                           replaced by the deposits) */
+  ABP_EVAL_GRID = 1     /* grid accumulated per eq. update / eq. Cupdate, read back by cubic
+                           Hermite interpolation */
+} abp_eval_mode;
+
+typedef enum {
+  ABP_CV_COM_DIST = 0,  /* distance between the centres of mass of two atom groups */
+  ABP_CV_TORSION = 1,   /* dihedral angle of four atoms, IUPAC sign, (-pi, pi] */
+  ABP_CV_RMSD_OFF = 2   /* offset RMSD of section "Definition of the RMSD" (no alignment) */
+} abp_cv_kind;
+
+/* Definition of the bias, fixed at abp_create. */
+typedef struct {
+  int32_t ndim;          /* CV dimension, 1..3 */
+  int32_t periodic[3];   /* 1: axis i is periodic on [lo_i, hi_i) with period hi_i - lo_i
+                            (minimum-image displacements) */
+  double lo[3], hi[3];   /* non-periodic axes: grid range [lo_i, hi_i], nodes at both ends */
+  int32_t kernel;        /* abp_kernel */
+  double width[3];       /* Gaussian: sigma_i > 0; compact: a_i > 0 (per-axis a, as the paper allows) */
+  int32_t p;             /* compact kernel exponent, 1..64 (ignored for Gaussian) */
+  int32_t transform;     /* abp_transform */
+  double kT;             /* beta^{-1} = k_B T in energy units (mABP) */
+  double b, c;           /* mABP parameters: 0 < b < 1, c >= 0 (eq. apfm) */
+  int32_t grid_n[3];     /* grid nodes per axis (>= 2 each), or all 0 for no grid.
+                            Periodic axis: nodes lo + j (hi-lo)/n, j < n.
+                            Non-periodic: nodes lo + j (hi-lo)/(n-1), j < n. */
+  int64_t capacity;      /* maximum number of hills the history holds, >= 1 */
+} abp_bias_desc;
+
+/* CV definition for a batch of nw walkers (device arrays, caller-owned).
+ * The atom lists of CV `a`, slot `t` (0 or 1), walker `w` are
+ *   list_idx[list_off[(a*2 + t)*(nw+1) + w] .. list_off[(a*2 + t)*(nw+1) + w + 1])
+ * holding walker-local atom indices (0 <= idx < n_atoms[w]).
+ *   COM_DIST: slot 0 = group A, slot 1 = group B, both non-empty and strictly increasing.
+ *   TORSION:  slot 0 = exactly 4 distinct atoms in dihedral order, slot 1 empty.
+ *   RMSD_OFF: slot 0 = the atoms, strictly increasing, non-empty; slot 1 empty.
+ *             ref_x/y/z[e] is the reference position of list entry e.
+ * CV a is coordinate a of the bias (ncv == ndim). TORSION requires a periodic
+ * axis; COM_DIST and RMSD_OFF require a non-periodic one. Positions are taken
+ * as unwrapped (no minimum image is applied between atoms). */
+typedef struct {
+  int32_t ncv;
+  int32_t kind[3];
+  const int32_t* list_off;
+  const int32_t* list_idx;
+  const float* ref_x;
+  const float* ref_y;
+  const float* ref_z;     /* may be NULL when no CV is RMSD_OFF */
+} abp_cv_desc;
+
+/* Walker pools (device, caller-owned, SoA FP32). Walker w owns atoms
+ * [atom_base[w], atom_base[w] + n_atoms[w]) of the pools. Walkers in one call
+ * must not share atoms. Forces are ACCUMULATED: f += bias force. */
+typedef struct {
+  int64_t nw;
+  const int64_t* atom_base;
+  const int32_t* n_atoms;
+  const float* x;
+  const float* y;
+  const float* z;
+  const float* mass;
+  float* fx;
+  float* fy;
+  float* fz;
+} abp_walkers;
+
+/* Create a context on HIP device `device`: allocates the hill history
+ * (capacity hills, FP64 master copy plus an FP32 working copy) and, if
+ * grid_n is set, the 2^ndim FP64 grid arrays (value, first and mixed
+ * derivatives), all zero (the initial condition h = h' = 0 of eq. update).
+ * Returns ABP_E_INVAL for a bad descriptor, ABP_E_NOMEM if allocation fails. */
+abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out);
+
+/* Wait for the context's work and free everything it owns. NULL is a no-op. */
+abp_status abp_destroy(abp_ctx* ctx);
+
+/* Append n hills (centers [ndim][n], heights [n], both `dtype`) to the
+ * history, in order, and add them to the grid if there is one (eq. update /
+ * eq. Cupdate summed over the batch). Heights must be finite and >= 0: a hill
+ * that is not gets height 0 and raises ABP_E_NONFINITE at abp_sync. Returns
+ * ABP_E_CAPACITY (nothing appended) if the history would overflow. n = 0 is a
+ * no-op. The appended hills are visible to work enqueued after this call on
+ * the same stream. */
+abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* centers,
+                        const void* heights, abp_stream stream);
+
+/* Evaluate the bias V and its gradient dV/ds at nq CV points q[ndim][nq].
+ * mode DIRECT sums hills [0, n_visible) (n_visible = -1: all committed
+ * hills); mode GRID interpolates the grid (n_visible must be -1) with
+ * tensor-product cubic Hermite polynomials from the value and derivative
+ * arrays, clamping non-periodic coordinates to [lo, hi].
+ * Outputs V[nq] and dVds[ndim][nq] have the same dtype as q.
+ * prec selects the hill-sum arithmetic; the grid path always uses FP64.
+ * The result for a query depends only on that query and the hills, not on nq
+ * or its position in the batch. nq = 0 is a no-op. */
+abp_status bias_eval(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, int64_t nq, abp_dtype dtype,
+                     const void* q, int64_t n_visible, void* V, void* dVds, abp_stream stream);
+
+/* Compute the CVs s[ncv][nw] (FP64) of a batch of walkers. COM reductions
+ * use FP64 accumulators. Walkers with invalid lists or non-finite inputs are
+ * skipped (s left unwritten) and flag the context's error word. */
+abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* walkers, double* s,
+                      abp_stream stream);
+
+/* The whole bias-force step for a batch of walkers, one fused launch:
+ * CVs -> bias and gradient at s (DIRECT: hills [0, n_visible[w]), or all
+ * committed hills if n_visible is NULL; GRID: interpolation) -> transform ->
+ * chain rule F_j += -sum_a dV/ds_a ds_a/dx_j on the CV atoms only.
+ * Writes s[ncv][nw], V[nw], dVds[ncv][nw] (FP64).
+ * deposit_slot (optional, [nw]): if deposit_slot[w] >= 0, the hill centred at
+ * walker w's s with height deposit_height[w] (NULL: 1.0) is written to that
+ * history slot, which must have been reserved with abp_reserve and is made
+ * visible by abp_commit. Atom lists must follow abp_cv_desc's rules. */
+abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
+                      const abp_walkers* walkers, const int64_t* n_visible,
+                      const int64_t* deposit_slot, const double* deposit_height,
+                      double* s, double* V, double* dVds, abp_stream stream);
+
+/* Reserve n history slots after every slot reserved so far (host-side
+ * bookkeeping, nothing enqueued). *first receives the first slot index.
+ * ABP_E_CAPACITY if the history would overflow. */
+abp_status abp_reserve(abp_ctx* ctx, int64_t n, int64_t* first);
+
+/* Make reserved slots [committed, upto) visible, in slot order, and add them
+ * to the grid if there is one. The writes into those slots (bias_force with
+ * deposit_slot) must be ordered before this call on `stream`. */
+abp_status abp_commit(abp_ctx* ctx, int64_t upto, abp_stream stream);
+
+/* Wait for `stream`, then return and clear the device error word. */
+abp_status abp_sync(abp_ctx* ctx, abp_stream stream);
+
+/* Number of committed (visible) hills; -1 for a NULL context. */
+int64_t abp_num_hills(const abp_ctx* ctx);
+
+/* Copy the committed history to HOST arrays centers[ndim][*n] and
+ * heights[*n] (FP64 master copy). On entry *n is the capacity of the host
+ * arrays; on return it is the number of hills copied. Synchronises the device. */
+abp_status abp_hills_export(abp_ctx* ctx, double* centers_host, double* heights_host, int64_t* n);
+
+/* Copy the grid to a HOST array H[nodes][2^ndim] (node index with axis 0
+ * fastest; entry m holds the derivative along every axis i whose bit is set
+ * in m). ABP_E_INVAL if the context has no grid. Synchronises the device. */
+abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
+
+/* Static message for a status code. */
+const char* abp_status_str(abp_status status);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* abp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,277 @@
+// Device-side helpers shared by the libabp kernels: working-form conversion
+// of CV coordinates, the per-hill arithmetic of the direct sum, compensated
+// accumulation, the bias transform and cubic Hermite interpolation.
+#pragma once
+
+#include "abp_internal.h"
+
+namespace abp {
+
+constexpr float kTinyGap = 0x1p-40f;   // floor of 1 - (delta/a)^2 in the FP32 compact kernel
+
+// ---------------------------------------------------------------------------
+// Working form of one CV coordinate (FP32 path).
+// Periodic axis: 32-bit fixed-point fraction of the period, so the unsigned
+// difference of two words is the minimum-image displacement mod 2^32.
+// Non-periodic axis: the bits of the FP32 value.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t work32(const Consts& K, int axis, double s) {
+  if (K.periodic[axis]) {
+    double t = (s - K.lo[axis]) * K.inv_period[axis];
+    t -= floor(t);
+    return (uint32_t)(uint64_t)rint(t * 4294967296.0);
+  }
+  return __float_as_uint((float)s);
+}
+
+// Working form in the FP64 path: turns on periodic axes (wrapped later).
+__device__ __forceinline__ double work64(const Consts& K, int axis, double s) {
+  return K.periodic[axis] ? (s - K.lo[axis]) * K.inv_period[axis] : s;
+}
+
+__device__ __forceinline__ uint32_t rec_word(const int4& h, int i) {
+  return (uint32_t)(i == 0 ? h.x : (i == 1 ? h.y : h.z));
+}
+
+// ---------------------------------------------------------------------------
+// One hill against one query, FP32. P[0] += w K; P[1+i] += w K * f_i where
+// f_i is the working displacement (Gaussian) or u/(1-u^2)^2 (compact); the
+// epilogue multiplies by the per-axis gradient scale. The height enters as
+// log2(w) in the exponent, so w K costs no separate multiply.
+// ---------------------------------------------------------------------------
+template <int D, int PMASK, int KERN>
+__device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, const float (&kf)[D],
+                                       const float (&ua)[D], float pl, float (&P)[D + 1]) {
+  float a = __int_as_float(h.w);
+  float d[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const uint32_t hc = rec_word(h, i);
+    if ((PMASK >> i) & 1)
+      d[i] = (float)(int32_t)(qw[i] - hc);
+    else
+      d[i] = __uint_as_float(qw[i]) - __uint_as_float(hc);
+  }
+  if (KERN == ABP_K_GAUSS) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) a = __builtin_fmaf(-d[i] * kf[i], d[i], a);
+    const float e = __builtin_amdgcn_exp2f(a);
+    P[0] += e;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fmaf(e, d[i], P[i + 1]);
+  } else {
+    float f[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      float u = d[i] * ua[i];
+      u = __builtin_fminf(__builtin_fmaxf(u, -2.0f), 2.0f);
+      const float t = u * u;
+      const float r = __builtin_amdgcn_rcpf(__builtin_fmaxf(1.0f - t, kTinyGap));
+      a = __builtin_fmaf(-pl, t * r, a);
+      f[i] = u * r * r;
+    }
+    const float e = __builtin_amdgcn_exp2f(a);
+    P[0] += e;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fmaf(e, f[i], P[i + 1]);
+  }
+}
+
+// Kahan step: fold a plainly summed chunk P into the compensated sum (S, C),
+// C carrying the rounding error of S with the opposite sign.
+template <int N>
+__device__ __forceinline__ void kahan_fold(float (&S)[N], float (&C)[N], float (&P)[N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const float y = P[r] - C[r];
+    const float t = S[r] + y;
+    C[r] = (t - S[r]) - y;
+    S[r] = t;
+    P[r] = 0.0f;
+  }
+}
+
+// One hill against one query, FP64. tc/tq are work64 coordinates; w the height.
+template <int D, int KERN>
+__device__ __forceinline__ void pair64(const Consts& K, const double (&tq)[D], const double4& h,
+                                       double (&P)[D + 1]) {
+  double d[D];
+  const double hc[3] = {h.x, h.y, h.z};
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double x = tq[i] - hc[i];
+    x -= K.per64[i] * rint(x);
+    d[i] = x;
+  }
+  if (KERN == ABP_K_GAUSS) {
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) a = __builtin_fma(d[i] * K.kf64[i], d[i], a);
+    const double we = h.w * exp2(-a);
+    P[0] += we;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fma(we, d[i], P[i + 1]);
+  } else {
+    double a = 0.0, f[D];
+    bool inside = true;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double u = d[i] * K.ua64[i];
+      const double t = u * u;
+      inside = inside && (t < 1.0);
+      const double r = 1.0 / (inside ? 1.0 - t : 1.0);
+      a = __builtin_fma(t, r, a);
+      f[i] = u * r * r;
+    }
+    const double we = inside ? h.w * exp2(-K.pl64 * a) : 0.0;
+    P[0] += we;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fma(we, f[i], P[i + 1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transform (eq. apfm, eq. btraj-grad) in FP64 on h and dh.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void apply_transform(const Consts& K, double h, const double (&dh)[D],
+                                                double& V, double (&dV)[D]) {
+  if (K.transform == ABP_T_MABP) {
+    const double den = 1.0 + K.c * (1.0 - K.b) * h;
+    V = K.kT * K.b / (1.0 - K.b) * log1p(K.c * (1.0 - K.b) * h);
+#pragma unroll
+    for (int i = 0; i < D; ++i) dV[i] = K.c * K.b * K.kT * dh[i] / den;
+  } else {
+    V = h;
+#pragma unroll
+    for (int i = 0; i < D; ++i) dV[i] = dh[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tensor-product cubic Hermite interpolation of the node arrays
+// grid[node][2^D] (value, first and mixed derivatives) at one point.
+// Returns h and the analytic gradient; *clamped is set when a non-periodic
+// coordinate lay outside [lo, hi].
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void hermite_eval(const Consts& K, const double* __restrict__ grid,
+                                             const double (&s)[D], double& h, double (&dh)[D],
+                                             bool& clamped) {
+  constexpr int NM = 1 << D;
+  int64_t j0[D], j1[D];
+  double A[D][2][2], B[D][2][2];   // basis for [cell end][datum: value/derivative]
+  clamped = false;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int64_t n = K.grid_n[i];
+    const double dx = K.grid_dx[i];
+    double x = s[i], t;
+    if (K.periodic[i]) {
+      // wrap into one period first, so any finite coordinate lands in a cell
+      double f = (x - K.lo[i]) * K.inv_period[i];
+      f -= floor(f);
+      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
+      const double u = f * (double)n;
+      int64_t j = (int64_t)u;
+      j = j > n - 1 ? n - 1 : j;
+      t = u - (double)j;
+      j0[i] = j;
+      j1[i] = (j + 1 == n) ? 0 : j + 1;
+    } else {
+      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
+      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
+      const double u = (x - K.lo[i]) / dx;
+      int64_t j = (int64_t)u;
+      j = j > n - 2 ? n - 2 : j;
+      j = j < 0 ? 0 : j;
+      t = u - (double)j;
+      j0[i] = j;
+      j1[i] = j + 1;
+    }
+    const double t2 = t * t, t3 = t2 * t;
+    // values of h00, h10 (times dx), h01, h11 (times dx) and their d/ds
+    A[i][0][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
+    A[i][0][1] = (t3 - 2.0 * t2 + t) * dx;
+    A[i][1][0] = -2.0 * t3 + 3.0 * t2;
+    A[i][1][1] = (t3 - t2) * dx;
+    B[i][0][0] = (6.0 * t2 - 6.0 * t) / dx;
+    B[i][0][1] = 3.0 * t2 - 4.0 * t + 1.0;
+    B[i][1][0] = (-6.0 * t2 + 6.0 * t) / dx;
+    B[i][1][1] = 3.0 * t2 - 2.0 * t;
+  }
+  double val = 0.0, g[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = 0.0;
+#pragma unroll
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    int64_t node = 0, stride = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      node += (((corner >> i) & 1) ? j1[i] : j0[i]) * stride;
+      stride *= K.grid_n[i];
+    }
+    double Hc[NM];
+    const double* src = grid + node * NM;
+    if (NM == 2) {
+      const double2 v = *reinterpret_cast<const double2*>(src);
+      Hc[0] = v.x; Hc[1] = v.y;
+    } else {
+#pragma unroll
+      for (int m = 0; m < NM; m += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(src + m);
+        Hc[m] = v.x; Hc[m + 1] = v.y;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      double wv = 1.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) wv *= A[i][(corner >> i) & 1][(m >> i) & 1];
+      val = __builtin_fma(wv, Hc[m], val);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double wg = 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+          wg *= (i == k) ? B[i][(corner >> i) & 1][(m >> i) & 1] : A[i][(corner >> i) & 1][(m >> i) & 1];
+        g[k] = __builtin_fma(wg, Hc[m], g[k]);
+      }
+    }
+  }
+  h = val;
+#pragma unroll
+  for (int k = 0; k < D; ++k) dh[k] = g[k];
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide FP64 sum in a fixed order (wave butterfly, then waves in order).
+// All threads of the block must call it; every thread gets the total.
+// `red` is LDS scratch of at least kBlock/64 * N doubles.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double x = v[r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[r] = x;
+  }
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) red[wave * N + r] = v[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w * N + r];
+    v[r] = t;
+  }
+  __syncthreads();
+}
+
+}  // namespace abp

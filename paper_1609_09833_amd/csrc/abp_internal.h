@@ -1,0 +1,113 @@
+// Internal declarations shared by the host layer and the HIP kernels of libabp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "abp.h"
+
+namespace abp {
+
+constexpr int kBlock = 256;      // threads per block for every kernel
+constexpr int kTile32 = 1024;    // hills per LDS tile in the FP32 direct sum (16 KiB)
+constexpr int kTile64 = 512;     // hills per LDS tile in the FP64 direct sum (16 KiB)
+constexpr int kChunk = 16;       // hills summed plainly before each compensated (Kahan) step
+
+// Device error word bits.
+enum : int32_t { kErrIndex = 1 << 0, kErrNonfinite = 1 << 1, kErrInval = 1 << 2 };
+
+// Per-context constants, computed once on the host from abp_bias_desc.
+//
+// Working displacements: in the FP32 path a periodic coordinate is held as a
+// 32-bit fixed-point fraction of its period, so the difference of two such
+// words (mod 2^32) is already the minimum image; converted to float it is a
+// displacement in units of L/2^32. A non-periodic coordinate is a float in
+// its own units. In the FP64 path periodic coordinates are fractions of the
+// period (turns) wrapped with rint; non-periodic ones are raw.
+struct Consts {
+  int32_t ndim, kernel, p, transform;
+  int32_t periodic[3];
+  double lo[3], hi[3], period[3], inv_period[3];
+  // FP32 path, per axis: Gaussian exponent factor on the working displacement
+  // (log2(e) unit^2 / (2 sigma^2)), compact scale (unit / a), gradient scale.
+  float kf32[3], ua32[3];
+  double gs32[3];
+  float pl32;                      // p log2(e), compact kernel
+  // FP64 path, the same in FP64 units.
+  double kf64[3], ua64[3], gs64[3], per64[3];
+  double pl64;
+  double kT, b, c;                 // mABP transform
+  double width[3];                 // sigma_i (Gaussian) or a_i (compact), real units
+  // grid
+  int32_t grid_n[3];
+  double grid_dx[3];               // node spacing per axis
+  int64_t nodes;
+};
+
+struct HistView {
+  double* c64;      // [ndim][capacity] master centers
+  double* w64;      // [capacity] master heights
+  int4* rec32;      // [capacity] FP32 working records {c0, c1, c2, log2(w)}
+  int64_t capacity;
+};
+
+// Kernel entry points (host-callable launchers). All enqueue on `stream`
+// and return hipSuccess or the launch error.
+hipError_t launch_hist_init(const HistView& H, int ndim, hipStream_t stream);
+
+hipError_t launch_hist_append(const Consts& K, const HistView& H, int64_t first, int64_t n,
+                              int dtype_f64, const void* centers, const void* heights,
+                              int32_t* err, hipStream_t stream);
+
+hipError_t launch_direct_sum(const Consts& K, const HistView& H, int64_t n_visible, abp_prec prec,
+                             int64_t nq, int q_f64, const void* q, void* V, void* dVds,
+                             hipStream_t stream);
+
+// Grid accumulation of hills [k0, k1) into the FP64 node arrays. `scratch`
+// must hold scratch_bytes_for(...) bytes (may be NULL when that is 0).
+size_t grid_deposit_scratch_bytes(const Consts& K, int64_t nhills);
+hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, int64_t k1,
+                               double* grid, double* scratch, hipStream_t stream);
+
+hipError_t launch_grid_eval(const Consts& K, const double* grid, int64_t nq, int q_f64,
+                            const void* q, void* V, void* dVds, unsigned long long* n_clamped,
+                            hipStream_t stream);
+
+struct ForceArgs {
+  int32_t ncv;
+  int32_t kind[3];
+  const int32_t* list_off;
+  const int32_t* list_idx;
+  const float* ref_x;
+  const float* ref_y;
+  const float* ref_z;
+  int64_t nw;
+  const int64_t* atom_base;
+  const int32_t* n_atoms;
+  const float* x;
+  const float* y;
+  const float* z;
+  const float* mass;
+  float* fx;
+  float* fy;
+  float* fz;
+  const int64_t* n_visible;        // [nw] or NULL
+  int64_t n_visible_default;       // used when n_visible is NULL
+  const int64_t* deposit_slot;     // [nw] or NULL
+  const double* deposit_height;    // [nw] or NULL
+  double* s;
+  double* V;
+  double* dVds;
+  int32_t cv_only;                 // 1: compute s only
+  int32_t use_grid;
+  int32_t prec;                    // abp_prec
+  const double* grid;
+  int32_t* err;
+};
+
+hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A,
+                             hipStream_t stream);
+
+}  // namespace abp
