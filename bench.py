@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU form "
@@ -94,6 +96,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        n = 1 << 28                                   # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copied 1 GiB three times")
+        return
     log("bench: generating the 2-D torsion workload (50,000 hills, 1,048,576 queries)")
     spec, hills, q = W.torsion_2d()
     nq, nh = q.shape[1], hills.n

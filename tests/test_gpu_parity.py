@@ -33,7 +33,9 @@ def make_ctx(spec, hills, capacity=None):
 def compare_eval(spec, hills, q, V, dV, tol, what, floor=0.0):
     Vo, dVo, sV, sG = oracle.bias_eval(spec, hills.centers, hills.heights, q)
     r0 = check_bound(f"{what} V", host(V) if hasattr(V, "cpu") else V, Vo, sV, tol, floor)
-    r1 = check_bound(f"{what} dV/ds", host(dV) if hasattr(dV, "cpu") else dV, dVo, sG, tol, floor)
+    # a flushed term's gradient is its value times at most |delta|/sigma^2 (or the compact analogue)
+    gfloor = floor * 1e4 * max(1.0, max(1.0 / w ** 2 for w in spec.width[:spec.ndim]))
+    r1 = check_bound(f"{what} dV/ds", host(dV) if hasattr(dV, "cpu") else dV, dVo, sG, tol, gfloor)
     return max(r0, r1)
 
 
