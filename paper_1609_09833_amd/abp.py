@@ -14,7 +14,7 @@ import os
 import torch  # loaded first so that libabp.so binds to the same HIP runtime as torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libabp.so")
+LIB_PATH = os.environ.get("ABP_LIB_PATH") or os.path.join(_PKG, "libabp.so")
 
 ABP_OK, ABP_E_INVAL, ABP_E_NOMEM, ABP_E_CAPACITY, ABP_E_DEVICE, ABP_E_INDEX, ABP_E_NONFINITE = range(7)
 ABP_F32, ABP_F64 = 0, 1

@@ -36,9 +36,9 @@ def sources():
     return out
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+def _compile(src, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 feature and says so; drop that line
     noise = "is not a recognized feature for this target"
@@ -46,26 +46,28 @@ def _compile(src):
     return src, obj, r.returncode, err
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, lib_path: str = LIB, extra=(), build_dir: str = BUILD) -> str:
+    """Compile and link. `extra` adds compiler flags (e.g. -D overrides of tile
+    constants) and `lib_path`/`build_dir` redirect the outputs, for variants."""
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), max(1, (os.cpu_count() or 4)), 16)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for src, obj, rc, err in ex.map(_compile, srcs):
+        for src, obj, rc, err in ex.map(lambda s: _compile(s, build_dir, tuple(extra)), srcs):
             if err.strip() and verbose:
                 print(err, file=sys.stderr)
             if rc != 0:
                 raise RuntimeError(f"hipcc failed on {src}")
             objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         print(r.stderr, file=sys.stderr)
         raise RuntimeError("link of libabp.so failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

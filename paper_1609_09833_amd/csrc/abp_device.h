@@ -38,8 +38,11 @@ __device__ __forceinline__ uint32_t rec_word(const int4& h, int i) {
 // f_i is the working displacement (Gaussian) or u/(1-u^2)^2 (compact); the
 // epilogue multiplies by the per-axis gradient scale. The height enters as
 // log2(w) in the exponent, so w K costs no separate multiply.
+// ISO: every axis has the same exponent factor kf[0], so the squared
+//      displacements are summed first and scaled once.
+// FIRST: the pair opens a new partial sum (P is assigned, not accumulated).
 // ---------------------------------------------------------------------------
-template <int D, int PMASK, int KERN>
+template <int D, int PMASK, int KERN, bool ISO = false, bool FIRST = false>
 __device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, const float (&kf)[D],
                                        const float (&ua)[D], float pl, float (&P)[D + 1]) {
   float a = __int_as_float(h.w);
@@ -52,15 +55,20 @@ __device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, c
     else
       d[i] = __uint_as_float(qw[i]) - __uint_as_float(hc);
   }
+  float f[D];
   if (KERN == ABP_K_GAUSS) {
+    if (ISO) {
+      float t = d[0] * d[0];
 #pragma unroll
-    for (int i = 0; i < D; ++i) a = __builtin_fmaf(-d[i] * kf[i], d[i], a);
-    const float e = __builtin_amdgcn_exp2f(a);
-    P[0] += e;
+      for (int i = 1; i < D; ++i) t = __builtin_fmaf(d[i], d[i], t);
+      a = __builtin_fmaf(-kf[0], t, a);
+    } else {
 #pragma unroll
-    for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fmaf(e, d[i], P[i + 1]);
+      for (int i = 0; i < D; ++i) a = __builtin_fmaf(-d[i] * kf[i], d[i], a);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) f[i] = d[i];
   } else {
-    float f[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       float u = d[i] * ua[i];
@@ -70,7 +78,13 @@ __device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, c
       a = __builtin_fmaf(-pl, t * r, a);
       f[i] = u * r * r;
     }
-    const float e = __builtin_amdgcn_exp2f(a);
+  }
+  const float e = __builtin_amdgcn_exp2f(a);
+  if (FIRST) {
+    P[0] = e;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i + 1] = e * f[i];
+  } else {
     P[0] += e;
 #pragma unroll
     for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fmaf(e, f[i], P[i + 1]);
@@ -78,16 +92,16 @@ __device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, c
 }
 
 // Kahan step: fold a plainly summed chunk P into the compensated sum (S, C),
-// C carrying the rounding error of S with the opposite sign.
+// C carrying the rounding error of S with the opposite sign. P is left as is
+// (the next chunk overwrites it).
 template <int N>
-__device__ __forceinline__ void kahan_fold(float (&S)[N], float (&C)[N], float (&P)[N]) {
+__device__ __forceinline__ void kahan_fold(float (&S)[N], float (&C)[N], const float (&P)[N]) {
 #pragma unroll
   for (int r = 0; r < N; ++r) {
     const float y = P[r] - C[r];
     const float t = S[r] + y;
     C[r] = (t - S[r]) - y;
     S[r] = t;
-    P[r] = 0.0f;
   }
 }
 

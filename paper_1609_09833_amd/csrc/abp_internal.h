@@ -13,7 +13,14 @@ namespace abp {
 constexpr int kBlock = 256;      // threads per block for every kernel
 constexpr int kTile32 = 1024;    // hills per LDS tile in the FP32 direct sum (16 KiB)
 constexpr int kTile64 = 512;     // hills per LDS tile in the FP64 direct sum (16 KiB)
-constexpr int kChunk = 16;       // hills summed plainly before each compensated (Kahan) step
+#ifndef ABP_CHUNK
+#define ABP_CHUNK 32
+#endif
+#ifndef ABP_Q2D
+#define ABP_Q2D 2
+#endif
+constexpr int kChunk = ABP_CHUNK; // hills summed plainly before each compensated (Kahan) step
+constexpr int kQ2D = ABP_Q2D;     // queries per thread in the 2-D/3-D FP32 direct sum
 
 // Device error word bits.
 enum : int32_t { kErrIndex = 1 << 0, kErrNonfinite = 1 << 1, kErrInval = 1 << 2 };
@@ -107,7 +114,16 @@ struct ForceArgs {
   int32_t* err;
 };
 
-hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A,
-                             hipStream_t stream);
+// Hills summed by one block of one walker in bias_force. Fixed, so the split
+// of a walker's sum never depends on the batch it is in.
+constexpr int kHillsPerBlock = 32768;
+
+// Blocks per walker the bias-force launch uses, and the bytes of partial sums
+// it needs (0 when one block per walker suffices). `arrivals` is an array of
+// nw counters that must be zero before the launch; the kernel leaves it zero.
+int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only);
+size_t force_partials_bytes(int64_t nw, int nbw, int ndim);
+hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* partials,
+                             unsigned int* arrivals, hipStream_t stream);
 
 }  // namespace abp
