@@ -29,10 +29,8 @@ struct abp_ctx {
   unsigned long long* clamped = nullptr;
   double* scratch = nullptr;
   size_t scratch_bytes = 0;
-  void* fpartials = nullptr;          // bias_force: per-block partial sums
-  size_t fpartials_bytes = 0;
-  unsigned int* farrivals = nullptr;  // bias_force: per-walker arrival counters, zero at rest
-  int64_t farrivals_n = 0;
+  void* fws = nullptr;                // bias_force: CV state, atom lists, partial sums
+  size_t fws_bytes = 0;
 
   HistView hist() const {
     HistView h;
@@ -224,29 +222,17 @@ abp_status grow_scratch(abp_ctx* ctx, size_t bytes) {
   return ABP_OK;
 }
 
-// Workspace of a multi-block bias_force launch (grow-only; counters zeroed
-// when allocated and left at zero by every launch).
+// Workspace of a direct-sum bias_force launch (grow-only).
 abp_status force_workspace(abp_ctx* ctx, int64_t nw, int nbw) {
-  const size_t pb = abp::force_partials_bytes(nw, nbw, ctx->desc.ndim);
+  const size_t pb = abp::force_workspace_bytes(nw, nbw, ctx->desc.ndim);
   if (pb == 0) return ABP_OK;
-  if (pb > ctx->fpartials_bytes) {
+  if (pb > ctx->fws_bytes) {
     HIP_TRY(hipDeviceSynchronize());
-    if (ctx->fpartials) HIP_TRY(hipFree(ctx->fpartials));
-    ctx->fpartials = nullptr;
-    ctx->fpartials_bytes = 0;
-    if (hipMalloc(&ctx->fpartials, pb) != hipSuccess) return fail(ABP_E_NOMEM, "cannot allocate bias_force workspace");
-    ctx->fpartials_bytes = pb;
-  }
-  if (nw > ctx->farrivals_n) {
-    HIP_TRY(hipDeviceSynchronize());
-    if (ctx->farrivals) HIP_TRY(hipFree(ctx->farrivals));
-    ctx->farrivals = nullptr;
-    ctx->farrivals_n = 0;
-    if (hipMalloc(&ctx->farrivals, sizeof(unsigned int) * nw) != hipSuccess)
-      return fail(ABP_E_NOMEM, "cannot allocate bias_force counters");
-    HIP_TRY(hipMemset(ctx->farrivals, 0, sizeof(unsigned int) * nw));
-    HIP_TRY(hipDeviceSynchronize());
-    ctx->farrivals_n = nw;
+    if (ctx->fws) HIP_TRY(hipFree(ctx->fws));
+    ctx->fws = nullptr;
+    ctx->fws_bytes = 0;
+    if (hipMalloc(&ctx->fws, pb) != hipSuccess) return fail(ABP_E_NOMEM, "cannot allocate bias_force workspace");
+    ctx->fws_bytes = pb;
   }
   return ABP_OK;
 }
@@ -269,8 +255,7 @@ void free_all(abp_ctx* ctx) {
   if (ctx->err) (void)hipFree(ctx->err);
   if (ctx->clamped) (void)hipFree(ctx->clamped);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
-  if (ctx->fpartials) (void)hipFree(ctx->fpartials);
-  if (ctx->farrivals) (void)hipFree(ctx->farrivals);
+  if (ctx->fws) (void)hipFree(ctx->fws);
 }
 
 }  // namespace
@@ -391,7 +376,7 @@ abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* wa
   A.s = s;
   A.cv_only = 1;
   A.prec = ABP_PREC_FP64;
-  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, nullptr, nullptr, (hipStream_t)stream));
+  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, nullptr, (hipStream_t)stream));
   return ok();
 }
 
@@ -420,10 +405,12 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
   A.use_grid = mode == ABP_EVAL_GRID ? 1 : 0;
   A.grid = ctx->grid;
   A.prec = prec;
-  const int nbw = abp::force_blocks_per_walker(ctx->committed, A.use_grid, 0);
-  st = force_workspace(ctx, walkers->nw, nbw);
-  if (st != ABP_OK) return st;
-  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, ctx->fpartials, ctx->farrivals, (hipStream_t)stream));
+  if (!A.use_grid) {
+    const int nbw = abp::force_blocks_per_walker(ctx->committed, 0, 0);
+    st = force_workspace(ctx, walkers->nw, nbw);
+    if (st != ABP_OK) return st;
+  }
+  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, ctx->fws, (hipStream_t)stream));
   return ok();
 }
 

@@ -85,7 +85,9 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, int64_t nq, int
 struct ForceArgs {
   int32_t ncv;
   int32_t kind[3];
-  const int32_t* list_off;
+  const int32_t* list_off;         // CSR offsets [(a*2+t)*(nw+1) + w], or
+  const int32_t* list_beg;         // start and length of list (a*2+t) of walker w at
+  const int32_t* list_len;         //   [(a*2+t)*nw + w] (used when list_beg is set)
   const int32_t* list_idx;
   const float* ref_x;
   const float* ref_y;
@@ -114,16 +116,15 @@ struct ForceArgs {
   int32_t* err;
 };
 
-// Hills summed by one block of one walker in bias_force. Fixed, so the split
-// of a walker's sum never depends on the batch it is in.
-constexpr int kHillsPerBlock = 32768;
+// Hills per chunk of a walker's sum in bias_force (one lane sums one chunk).
+// Fixed, so the split of a walker's sum never depends on the batch it is in.
+constexpr int kHillsPerBlock = 256;
 
-// Blocks per walker the bias-force launch uses, and the bytes of partial sums
-// it needs (0 when one block per walker suffices). `arrivals` is an array of
-// nw counters that must be zero before the launch; the kernel leaves it zero.
+// Chunks per walker of the sum stage, and the workspace bytes a direct-sum
+// bias_force launch needs (CV state, cached atom lists, chunk partials).
 int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only);
-size_t force_partials_bytes(int64_t nw, int nbw, int ndim);
-hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* partials,
-                             unsigned int* arrivals, hipStream_t stream);
+size_t force_workspace_bytes(int64_t nw, int nbw, int ndim);
+hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* workspace,
+                             hipStream_t stream);
 
 }  // namespace abp
