@@ -74,12 +74,88 @@ def cpu_baseline(spec, hills, q, target_s=15.0):
                       f"{dt:.1f} s"}
 
 
+def serving_leg(abp, W, torch, window_s=1.0):
+    """The serving workload: 4,096 walkers of 1,000-20,000 atoms (COM distance
+    + torsion CVs), Poisson arrivals at 200,000 requests/s to uniformly chosen
+    walkers, a deposit every 500th step of a walker (heights 1.2 exp(-k/20000)),
+    2-D history pre-seeded to 0, 100,000 and 200,000 hills. Latency is arrival
+    to observed completion on the host clock."""
+    import numpy as np
+    rate, n_walkers, period = 200_000.0, 4096, 500
+    log("bench: serving: generating 4,096 walkers of 1,000-20,000 atoms")
+    wk = W.ligand_pocket_walkers(seed=11, n_walkers=n_walkers, atoms_lo=1000, atoms_hi=20000)
+    spec, seed_hills = W.serving_hills(seed=11, n_hills=200_000)
+    ctx = abp.Context(spec, capacity=260_000)
+    dev = torch.device("cuda", 0)
+    cen = torch.as_tensor(seed_hills.centers, device=dev)
+    hts = torch.as_tensor(seed_hills.heights, device=dev)
+    state = {"seeded": 0}
+
+    def seed_to(n):
+        k = state["seeded"]
+        have = ctx.num_hills
+        if n > have:
+            take = n - have
+            abp.bias_deposit(ctx, cen[:, k:k + take].contiguous(), hts[k:k + take].contiguous())
+            state["seeded"] = k + take
+        torch.cuda.synchronize()
+
+    def server(budget, max_batch, streams):
+        srv = abp.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=max_batch, streams=streams,
+                         deposit_every=period, height0=1.2, height_decay=20000.0, amplitude=2.0 ** -7)
+        for w in range(wk.nw):
+            b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+            lens, idx, rx, ry, rz = W.walker_lists(wk, w)
+            srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx)
+        return srv
+
+    def run(srv, name, n_req, seed, req_rate=rate):
+        t, w, step = W.serving_requests(seed=seed, n_walkers=n_walkers, rate=req_rate, n_requests=n_req,
+                                        phase=period)
+        if req_rate > 1e8:
+            t = np.zeros_like(t)
+        out = srv.replay(w, step, t)
+        st = out["stats"]
+        lat = (out["t_done"] - t) * 1e6
+        r = {"requests": n_req, "offered_req_per_s": None if req_rate > 1e8 else req_rate,
+             "completed_req_per_s": n_req / st["wall_seconds"],
+             "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+             "p999_us": float(np.percentile(lat, 99.9)), "batches": st["batches"],
+             "mean_batch": n_req / max(st["batches"], 1), "max_batch": st["max_batch_seen"],
+             "admissions": st["admissions"], "evictions": st["evictions"], "deposits": st["deposits"],
+             "peak_resident_walkers": st["peak_resident"],
+             "hills_seen": [int(out["version"].min()), int(out["version"].max())]}
+        log(f"bench: serving {name}: {r['completed_req_per_s']:.4g} req/s, p50 {r['p50_us']:.1f} us, "
+            f"p99 {r['p99_us']:.1f} us, mean batch {r['mean_batch']:.1f}, evictions {r['evictions']}")
+        return r
+
+    res = {}
+    n_win = int(rate * window_s)
+    budget = 512 << 20
+    srv = server(budget, 1024, 3)
+    for i, hist in enumerate((0, 100_000, 200_000)):
+        seed_to(hist)
+        res[f"hist{hist // 1000}k_budget512MiB"] = run(srv, f"{hist} hills, 512 MiB", n_win, 100 + i)
+    res["hist200k_budget512MiB_saturated"] = run(srv, "saturated", n_win, 110, req_rate=1e12)
+    srv.close()
+    srv = server(8 << 30, 1024, 3)
+    res["hist200k_unlimited"] = run(srv, "200k hills, all resident", n_win, 120)
+    srv.close()
+    srv = server(8 << 30, 1, 4)
+    res["hist200k_plain_launches"] = run(srv, "plain per-walker launches", n_win // 10, 130)
+    res["hist200k_plain_launches_saturated"] = run(srv, "plain saturated", n_win // 10, 131, req_rate=1e12)
+    srv.close()
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -198,9 +274,23 @@ def main():
                        "walkers": wk.nw, "hills": fhills.n}
         log(f"bench: {name} {wk.nw * args.steps / el4:.4e} walker-steps/s")
     abp.abp_sync(fctx)
+    del fctx, dw
+    if not args.no_serving:
+        sv = serving_leg(abp, W, torch)
+        head = sv["hist200k_budget512MiB"]
+        out["serving"] = {"workload": "4,096 walkers of 1,000-20,000 atoms, Poisson 200k req/s, 200k-hill "
+                                      "history, 512 MiB walker budget, batched",
+                          "p50_us": head["p50_us"], "p99_us": head["p99_us"], "p999_us": head["p999_us"],
+                          "completed_req_per_s": head["completed_req_per_s"],
+                          "plain_launch_p99_us": sv["hist200k_plain_launches"]["p99_us"],
+                          "plain_launch_capacity_req_per_s":
+                              sv["hist200k_plain_launches_saturated"]["completed_req_per_s"],
+                          "batched_capacity_req_per_s":
+                              sv["hist200k_budget512MiB_saturated"]["completed_req_per_s"]}
+        extra["serving"] = sv
     out["extra"] = extra
     out["valu_issue"] = {"lane_ops_per_s_peak": VALU_LANE_OPS,
-                         "note": "non-packed VALU issue rate; see DESIGN.md for the per-pair instruction count"}
+                         "note": "non-packed VALU issue rate, 256 CU x 64 lanes x 2.4 GHz"}
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(spec, hills, q)

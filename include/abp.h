@@ -222,6 +222,83 @@ abp_status abp_hills_export(abp_ctx* ctx, double* centers_host, double* heights_
  * in m). ABP_E_INVAL if the context has no grid. Synchronises the device. */
 abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
 
+/* ---- Serving loop -------------------------------------------------------
+ * Continuous batching of bias-force requests from many walkers (MD replicas)
+ * that share the context's hill history. Not in the paper (one walker per MD
+ * engine there); it serves the same per-step problem to many engines at once.
+ *
+ * Each walker's engine state (positions, masses and forces of all its atoms,
+ * 28 bytes per atom) lives in device memory while the walker is admitted.
+ * Walkers are admitted first come first served against an HBM budget; when
+ * memory is short the least recently used idle walker is evicted. A request
+ * (walker, step) is evaluated against the hills committed when its batch is
+ * formed (its version). A request whose step is a positive multiple of
+ * deposit_every deposits a hill at its CV value into a history slot reserved
+ * in batch-formation order; slots are committed once every earlier slot is
+ * done. A walker has at most one request in flight; up to `streams` batches
+ * run at once, each formed from whatever requests are ready when a stream
+ * frees up. Positions for a step come from a synthetic engine step on the
+ * device: base positions plus amplitude * u, u in [-1, 1) hashed from
+ * (walker, step, atom, coordinate). The bias path itself is bias_force's. */
+typedef struct abp_server abp_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device memory for walker engine state (28 bytes per atom) */
+  int32_t max_batch;         /* requests per batch, >= 1 (1 = one launch per request) */
+  int32_t streams;           /* batches in flight, 1..8 */
+  int32_t deposit_every;     /* deposit period in steps; 0: never */
+  int32_t prec;              /* abp_prec of the hill sum */
+  double height0;            /* deposit height height0 * exp(-k / height_decay) for slot k */
+  double height_decay;       /* 0: constant height0 */
+  float amplitude;           /* synthetic engine displacement bound, nm (power of two: exact) */
+  int32_t cv_kind[3];        /* abp_cv_kind of CV a (a < ndim), same rules as abp_cv_desc.kind */
+} abp_server_desc;
+
+typedef struct {
+  int64_t completed;         /* requests done */
+  int64_t batches;           /* launches of the bias-force path */
+  int64_t max_batch_seen;
+  int64_t admissions;        /* walkers brought into device memory */
+  int64_t evictions;
+  int64_t deposits;          /* hills committed by requests */
+  int64_t peak_resident;     /* most walkers resident at once */
+  int64_t pool_atoms;        /* atoms the budget holds */
+  double wall_seconds;       /* replay wall time */
+} abp_server_stats;
+
+/* Create a server on a context (DIRECT sums only). ABP_E_INVAL for a bad
+ * descriptor, ABP_E_NOMEM if the budget or the per-batch buffers cannot be
+ * allocated. */
+abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_server** out);
+
+/* Wait for outstanding work and free the server (not the context). */
+abp_status abp_server_destroy(abp_server* srv);
+
+/* Register a walker (HOST arrays, copied): n_atoms base positions x0/y0/z0
+ * and masses; list_len[2*ncv] lengths of the CV lists (CV a, slot t at
+ * 2a+t, rules as in abp_cv_desc) and list_idx their concatenation in that
+ * order; ref_x/y/z aligned with list_idx (NULL when no CV is RMSD_OFF).
+ * Lists are checked here (ABP_E_INVAL); a walker whose state exceeds the
+ * whole budget is refused with ABP_E_NOMEM. *walker_id receives its id. */
+abp_status abp_server_add_walker(abp_server* srv, int32_t n_atoms, const float* x0, const float* y0,
+                                 const float* z0, const float* mass, const int32_t* list_len,
+                                 const int32_t* list_idx, const float* ref_x, const float* ref_y,
+                                 const float* ref_z, int32_t* walker_id);
+
+/* Replay an open-loop schedule of n requests (HOST arrays): walker[i] at
+ * step[i] arrives t_arrival[i] seconds after the call starts (sorted,
+ * non-decreasing); a walker's steps must increase. Blocks until every request
+ * is done. Outputs (HOST arrays, each may be NULL): t_done[i] seconds when
+ * completion was observed; version[i] hills visible to the request;
+ * deposit_slot[i] history slot it deposited into or -1; s[ncv][n], V[n],
+ * dVds[ncv][n]. */
+abp_status abp_server_replay(abp_server* srv, int64_t n, const int32_t* walker, const int64_t* step,
+                             const double* t_arrival, double* t_done, int64_t* version, int64_t* deposit_slot,
+                             double* s, double* V, double* dVds);
+
+/* Counters of the last replay. */
+abp_status abp_server_get_stats(abp_server* srv, abp_server_stats* out);
+
 /* Static message for a status code. */
 const char* abp_status_str(abp_status status);
 

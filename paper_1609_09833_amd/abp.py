@@ -26,7 +26,9 @@ ABP_CV_COM_DIST, ABP_CV_TORSION, ABP_CV_RMSD_OFF = 0, 1, 2
 
 EXPORTED = ("abp_create", "abp_destroy", "bias_deposit", "bias_eval", "cv_compute", "bias_force",
             "abp_reserve", "abp_commit", "abp_sync", "abp_num_hills", "abp_hills_export",
-            "abp_grid_export", "abp_status_str", "abp_last_error")
+            "abp_grid_export", "abp_status_str", "abp_last_error",
+            "abp_server_create", "abp_server_destroy", "abp_server_add_walker", "abp_server_replay",
+            "abp_server_get_stats")
 
 
 class AbpError(RuntimeError):
@@ -55,6 +57,18 @@ class WalkersDesc(C.Structure):
                 ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p)]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32),
+                ("deposit_every", C.c_int32), ("prec", C.c_int32), ("height0", C.c_double),
+                ("height_decay", C.c_double), ("amplitude", C.c_float), ("cv_kind", C.c_int32 * 3)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("batches", C.c_int64), ("max_batch_seen", C.c_int64),
+                ("admissions", C.c_int64), ("evictions", C.c_int64), ("deposits", C.c_int64),
+                ("peak_resident", C.c_int64), ("pool_atoms", C.c_int64), ("wall_seconds", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libabp.so not built at {LIB_PATH}: run __graft_entry__.build()")
@@ -75,6 +89,11 @@ def _load():
         "abp_grid_export": ([P, P, i64], i32),
         "abp_status_str": ([i32], C.c_char_p),
         "abp_last_error": ([], C.c_char_p),
+        "abp_server_create": ([P, P, P], i32),
+        "abp_server_destroy": ([P], i32),
+        "abp_server_add_walker": ([P, i32, P, P, P, P, P, P, P, P, P, P], i32),
+        "abp_server_replay": ([P, i64, P, P, P, P, P, P, P, P, P], i32),
+        "abp_server_get_stats": ([P, P], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -309,3 +328,81 @@ def abp_grid_export(ctx):
     H = np.zeros((nodes, 1 << ctx.ndim), dtype=np.float64)
     _check(lib.abp_grid_export(ctx.handle, H.ctypes.data_as(C.c_void_p), H.size))
     return H
+
+
+class Server:
+    """An abp_server: continuous batching of bias-force requests from many
+    walkers over one context's hill history (HOST-side inputs and outputs)."""
+
+    def __init__(self, ctx, kinds, hbm_budget_bytes=1 << 30, max_batch=1024, streams=2, deposit_every=0,
+                 prec=ABP_PREC_FP32_KAHAN, height0=0.0, height_decay=0.0, amplitude=0.0078125):
+        self.ctx = ctx
+        d = ServerDesc()
+        d.hbm_budget_bytes, d.max_batch, d.streams = int(hbm_budget_bytes), int(max_batch), int(streams)
+        d.deposit_every, d.prec = int(deposit_every), int(prec)
+        d.height0, d.height_decay, d.amplitude = float(height0), float(height_decay), float(amplitude)
+        for i in range(3):
+            d.cv_kind[i] = int(kinds[i]) if i < len(kinds) else 0
+        self.desc = d
+        self.ncv = ctx.ndim
+        h = C.c_void_p()
+        _check(lib.abp_server_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib.abp_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_walker(self, x0, y0, z0, mass, list_len, list_idx, ref_x=None, ref_y=None, ref_z=None):
+        import numpy as np
+        f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+        x0, y0, z0, mass = f32(x0), f32(y0), f32(z0), f32(mass)
+        ll = np.ascontiguousarray(list_len, dtype=np.int32)
+        li = np.ascontiguousarray(list_idx, dtype=np.int32)
+        if ll.shape != (2 * self.ncv,):
+            raise ValueError("list_len must hold 2*ncv lengths")
+        refs = [None if r is None else f32(r) for r in (ref_x, ref_y, ref_z)]
+        p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        wid = C.c_int32()
+        _check(lib.abp_server_add_walker(self.handle, int(x0.shape[0]), p(x0), p(y0), p(z0), p(mass), p(ll),
+                                         p(li if li.size else np.zeros(1, np.int32)), p(refs[0]), p(refs[1]),
+                                         p(refs[2]), C.byref(wid)))
+        return wid.value
+
+    def replay(self, walker, step, t_arrival):
+        """Run an open-loop schedule; returns a dict of per-request numpy arrays
+        (t_done, version, deposit_slot, s[ncv][n], V, dVds[ncv][n]) and stats."""
+        import numpy as np
+        w = np.ascontiguousarray(walker, dtype=np.int32)
+        st = np.ascontiguousarray(step, dtype=np.int64)
+        ta = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        n = int(w.shape[0])
+        m = max(n, 1)
+        out = {
+            "t_done": np.full(m, np.nan), "version": np.full(m, -1, np.int64),
+            "deposit_slot": np.full(m, -2, np.int64), "s": np.full((self.ncv, m), np.nan),
+            "V": np.full(m, np.nan), "dVds": np.full((self.ncv, m), np.nan),
+        }
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        s_buf = np.full(self.ncv * m, np.nan)
+        d_buf = np.full(self.ncv * m, np.nan)
+        _check(lib.abp_server_replay(self.handle, n, p(w), p(st), p(ta), p(out["t_done"]), p(out["version"]),
+                                     p(out["deposit_slot"]), p(s_buf), p(out["V"]), p(d_buf)))
+        out["s"] = s_buf[: self.ncv * n].reshape(self.ncv, n)
+        out["dVds"] = d_buf[: self.ncv * n].reshape(self.ncv, n)
+        for k in ("t_done", "version", "deposit_slot", "V"):
+            out[k] = out[k][:n]
+        out["stats"] = self.stats()
+        return out
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib.abp_server_get_stats(self.handle, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerStats._fields_}

@@ -10,7 +10,7 @@
 #include <new>
 #include <string>
 
-#include "abp_internal.h"
+#include "abp_serve_internal.h"
 
 using abp::Consts;
 using abp::HistView;
@@ -498,3 +498,23 @@ const char* abp_status_str(abp_status status) {
 const char* abp_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+namespace abp {
+
+CtxView ctx_view(abp_ctx* ctx) {
+  CtxView v;
+  v.K = ctx->K;
+  v.H = ctx->hist();
+  v.err = ctx->err;
+  v.device = ctx->device;
+  return v;
+}
+
+int64_t ctx_reserved(const abp_ctx* ctx) { return ctx->reserved; }
+
+abp_status set_error(abp_status st, const char* msg) {
+  if (st == ABP_OK) return ok();
+  return fail(st, "%s", msg);
+}
+
+}  // namespace abp

@@ -1,0 +1,48 @@
+// Internal declarations of the serving loop (host scheduler and device engine step).
+#pragma once
+
+#include "abp_internal.h"
+
+namespace abp {
+
+struct EngineArgs {
+  int64_t nb;                  // requests in the batch
+  const int64_t* atom_base;    // [nb] device offset of the walker's atoms in the pools
+  const int32_t* n_atoms;      // [nb]
+  const int64_t* host_base;    // [nb] offset of the walker's atoms in the host arrays
+  const int32_t* fresh;        // [nb] 1: walker admitted for this batch (initialise masses, forces)
+  const int32_t* walker;       // [nb] walker id (hash input)
+  const int64_t* step;         // [nb] MD step (hash input)
+  int32_t nlists;              // 2 * ncv
+  const int32_t* list_beg;     // [nlists][nb] into list_idx
+  const int32_t* list_len;     // [nlists][nb]
+  const int32_t* list_idx;     // device list pool
+  const float* h_x0;           // mapped pinned host: base positions and masses of every walker
+  const float* h_y0;
+  const float* h_z0;
+  const float* h_mass;
+  float amplitude;             // nm; positions move by at most this much from x0
+  float* x;                    // device pools
+  float* y;
+  float* z;
+  float* mass;
+  float* fx;
+  float* fy;
+  float* fz;
+};
+
+hipError_t launch_engine_step(const EngineArgs& E, hipStream_t stream);
+
+// The context pieces the server needs (defined by the host layer).
+struct CtxView {
+  Consts K;
+  HistView H;
+  int32_t* err;
+  int device;
+};
+CtxView ctx_view(abp_ctx* ctx);
+int64_t ctx_reserved(const abp_ctx* ctx);
+// Sets the calling thread's last-error message (read by abp_last_error).
+abp_status set_error(abp_status st, const char* msg);
+
+}  // namespace abp

@@ -325,3 +325,106 @@ def serving_schedule(seed=0, n_walkers=4096, rate=200_000.0, n_requests=200_000)
 def decaying_height(k):
     """Height law 1.2*exp(-k/20000) for hill index k (a workload choice, in kJ/mol)."""
     return 1.2 * np.exp(-np.asarray(k, dtype=np.float64) / 20000.0)
+
+
+# ---------------------------------------------------------------------------
+# Serving workloads: many walkers, requests arriving over time
+# ---------------------------------------------------------------------------
+
+def walker_lists(wk, w):
+    """CV lists of walker w in registration form: (list_len[2*ncv] int32,
+    list_idx int32, ref_x, ref_y, ref_z float32), lists in (cv, slot) order."""
+    lens, idx, rx, ry, rz = [], [], [], [], []
+    for a in range(wk.ncv):
+        for t in range(2):
+            lo, hi = int(wk.list_off[a, t, w]), int(wk.list_off[a, t, w + 1])
+            lens.append(hi - lo)
+            idx.append(wk.list_idx[lo:hi])
+            rx.append(wk.ref_x[lo:hi])
+            ry.append(wk.ref_y[lo:hi])
+            rz.append(wk.ref_z[lo:hi])
+    cat = lambda parts, dt: np.concatenate(parts).astype(dt) if parts else np.zeros(0, dt)
+    return (np.array(lens, dtype=np.int32), cat(idx, np.int32), cat(rx, np.float32), cat(ry, np.float32),
+            cat(rz, np.float32))
+
+
+def single_walker(wk, w, x=None, y=None, z=None):
+    """Walker w of a batch as a batch of its own (lists re-based, same atom
+    order); x/y/z replace its positions when given."""
+    b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+    lens, idx, rx, ry, rz = walker_lists(wk, w)
+    off = np.zeros((wk.ncv, 2, 2), dtype=np.int32)
+    pos = 0
+    for q, ln in enumerate(lens):
+        off[q // 2, q % 2] = (pos, pos + int(ln))
+        pos += int(ln)
+    pick = lambda given, pool: (pool[b:b + n] if given is None else given).astype(np.float32).copy()
+    return Walkers(n_atoms=wk.n_atoms[w:w + 1].copy(), atom_base=np.zeros(1, np.int64),
+                   x=pick(x, wk.x), y=pick(y, wk.y), z=pick(z, wk.z), mass=wk.mass[b:b + n].copy(),
+                   kinds=wk.kinds, list_off=off, list_idx=idx, ref_x=rx, ref_y=ry, ref_z=rz)
+
+
+def serving_requests(seed=0, n_walkers=1024, rate=200_000.0, n_requests=20_000, phase=0):
+    """Open-loop schedule for the serving loop: (t_arrival, walker, step).
+
+    Arrivals and walkers as in serving_schedule. Each walker's steps count up
+    by one per request from a start of 1 + U{0..phase-1} (phase = 0: start at
+    1), so a deposit period of `phase` steps is met by a fraction of the
+    walkers within a short window. Draw order: serving_schedule's, then the
+    start offsets.
+    """
+    t, w = serving_schedule(seed, n_walkers, rate, n_requests)
+    start = np.ones(n_walkers, dtype=np.int64)
+    if phase > 0:
+        start += np.random.default_rng(seed + 11).integers(0, phase, size=n_walkers)
+    step = np.zeros(n_requests, dtype=np.int64)
+    count = np.zeros(n_walkers, dtype=np.int64)
+    for i, wi in enumerate(w):
+        step[i] = start[wi] + count[wi]
+        count[wi] += 1
+    return t, w, step
+
+
+def serving_hills(seed=0, n_hills=200_000):
+    """Pre-seeded history for the serving workload: centers as in
+    ligand_pocket_hills, height of hill k from decaying_height(k)."""
+    spec, hills = ligand_pocket_hills(seed, n_hills)
+    return spec, Hills(hills.centers, decaying_height(np.arange(n_hills)))
+
+
+def _mix32(h):
+    """The 'lowbias32' integer mixer (C. Wellons, 2018) on uint32 arrays."""
+    h = np.asarray(h, dtype=np.uint32)
+    h = h ^ (h >> np.uint32(16))
+    h = h * np.uint32(0x7FEB352D)
+    h = h ^ (h >> np.uint32(15))
+    h = h * np.uint32(0x846CA68B)
+    h = h ^ (h >> np.uint32(16))
+    return h
+
+
+def engine_unit(walker, step, atom, coord):
+    """u in [-1, 1) (multiples of 2^-15) of the synthetic engine step for
+    (walker, step, atom, coordinate); arrays broadcast, all taken mod 2^32."""
+    u32 = lambda v: (np.atleast_1d(np.asarray(v, dtype=np.int64)) & 0xFFFFFFFF).astype(np.uint32)
+    inner = _mix32(u32(atom) * np.uint32(0xC2B2AE3D) + u32(coord))
+    mid = _mix32((u32(step) * np.uint32(0x85EBCA77)) ^ inner)
+    h = _mix32((u32(walker) * np.uint32(0x9E3779B1)) ^ mid)
+    k = ((h >> np.uint32(16)) & np.uint32(0xFFFF)).astype(np.float32)
+    return k * np.float32(1.0 / 32768.0) - np.float32(1.0)
+
+
+def engine_positions(x0, y0, z0, walker, step, atoms, amplitude):
+    """Positions the synthetic engine writes for `atoms` of a walker at a step:
+    x0 + amplitude * u in float32 with round-to-nearest per operation (the
+    device writes the same bits). Returns copies of x0/y0/z0 with those atoms
+    replaced."""
+    amp = np.float32(amplitude)
+    out = []
+    atoms = np.unique(np.asarray(atoms, dtype=np.int64))
+    for c, base in enumerate((x0, y0, z0)):
+        p = np.asarray(base, dtype=np.float32).copy()
+        u = engine_unit(walker, step, atoms, c)
+        p[atoms] = p[atoms] + (amp * u).astype(np.float32)
+        out.append(p)
+    return out

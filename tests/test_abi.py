@@ -55,6 +55,9 @@ int main(void) {
          offsetof(abp_bias_desc, grid_n), offsetof(abp_bias_desc, kT));
   printf("%zu %zu %zu\\n", sizeof(abp_cv_desc), offsetof(abp_cv_desc, list_off), offsetof(abp_cv_desc, ref_z));
   printf("%zu %zu %zu\\n", sizeof(abp_walkers), offsetof(abp_walkers, x), offsetof(abp_walkers, fz));
+  printf("%zu %zu %zu\\n", sizeof(abp_server_desc), offsetof(abp_server_desc, amplitude),
+         offsetof(abp_server_desc, cv_kind));
+  printf("%zu %zu\\n", sizeof(abp_server_stats), offsetof(abp_server_stats, wall_seconds));
   return 0;
 }
 """)
@@ -68,6 +71,8 @@ int main(void) {
                        abp.BiasDesc.kT.offset]
     assert vals[1] == [C.sizeof(abp.CvDesc), abp.CvDesc.list_off.offset, abp.CvDesc.ref_z.offset]
     assert vals[2] == [C.sizeof(abp.WalkersDesc), abp.WalkersDesc.x.offset, abp.WalkersDesc.fz.offset]
+    assert vals[3] == [C.sizeof(abp.ServerDesc), abp.ServerDesc.amplitude.offset, abp.ServerDesc.cv_kind.offset]
+    assert vals[4] == [C.sizeof(abp.ServerStats), abp.ServerStats.wall_seconds.offset]
 
 
 def test_host_side_validation_without_gpu(lib):

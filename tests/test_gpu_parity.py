@@ -344,23 +344,7 @@ def test_c3_grid_bias_force(c3):
 
 def extract_walker(wk, w):
     """Walker w of a batch as a batch of its own (lists re-based, same atom order)."""
-    b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
-    off = np.zeros((wk.ncv, 2, 2), dtype=np.int32)
-    idx, rx, ry, rz = [], [], [], []
-    pos = 0
-    for a in range(wk.ncv):
-        for t in range(2):
-            lo, hi = int(wk.list_off[a, t, w]), int(wk.list_off[a, t, w + 1])
-            off[a, t] = (pos, pos + hi - lo)
-            pos += hi - lo
-            idx.append(wk.list_idx[lo:hi])
-            rx.append(wk.ref_x[lo:hi]); ry.append(wk.ref_y[lo:hi]); rz.append(wk.ref_z[lo:hi])
-    cat = lambda l, dt: np.concatenate(l).astype(dt)
-    return W.Walkers(n_atoms=wk.n_atoms[w:w + 1].copy(), atom_base=np.zeros(1, np.int64),
-                     x=wk.x[b:b + n].copy(), y=wk.y[b:b + n].copy(), z=wk.z[b:b + n].copy(),
-                     mass=wk.mass[b:b + n].copy(), kinds=wk.kinds, list_off=off,
-                     list_idx=cat(idx, np.int32), ref_x=cat(rx, np.float32), ref_y=cat(ry, np.float32),
-                     ref_z=cat(rz, np.float32))
+    return W.single_walker(wk, w)
 
 
 def test_c3_alone_equals_in_the_mix(c3):

@@ -1,0 +1,175 @@
+"""GPU tests of the serving loop (abp_server_*): continuous batching of
+bias-force requests from many walkers sharing one hill history.
+
+Every request is re-evaluated by the oracle on the host: the walker's
+positions at that step are reproduced bit for bit from the synthetic engine's
+hash, the hills it saw are the first `version` hills of the exported history,
+and s, V and dV/ds must agree to the same bounds as a direct bias_force call.
+Deposits must land in the slots they report, with the reported CV value as
+center and the height law's height.
+"""
+import numpy as np
+import pytest
+
+from paper_1609_09833_amd import workloads as W
+from tests.gpu_common import device
+from tests.tolerance import check_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    device()
+    from paper_1609_09833_amd import abp as _abp
+    return _abp
+
+
+AMP = 2.0 ** -7          # nm, exact in float32
+N_WALKERS = 48
+N_HILLS = 5000
+
+
+def _setup(lib, n_hills=N_HILLS, capacity_extra=4096):
+    import torch
+    spec, hills = W.ligand_pocket_hills(seed=3, n_hills=n_hills)
+    wk = W.ligand_pocket_walkers(seed=5, n_walkers=N_WALKERS)
+    ctx = lib.Context(spec, n_hills + capacity_extra)
+    lib.bias_deposit(ctx, torch.tensor(hills.centers, dtype=torch.float64, device="cuda"),
+                     torch.tensor(hills.heights, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    return spec, hills, wk, ctx
+
+
+def _register(srv, wk):
+    ids = []
+    for w in range(wk.nw):
+        b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+        lens, idx, rx, ry, rz = W.walker_lists(wk, w)
+        ids.append(srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx,
+                                  rx, ry, rz))
+    assert ids == list(range(wk.nw))
+
+
+def _oracle_request(spec, centers, heights, wk, w, step, version):
+    from oracle import bias_eval, bias_force
+    b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+    lens, idx, _, _, _ = W.walker_lists(wk, w)
+    x, y, z = W.engine_positions(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], w, step, idx, AMP)
+    one = W.single_walker(wk, w, x, y, z)
+    zero = np.zeros(n)
+    c, h = centers[:, :version], heights[:version]
+    s, V, dV, _, _, _, status = bias_force(spec, c, h, one, zero, zero, zero)
+    assert status[0] == 0
+    _, _, sA0, sA = bias_eval(spec, c, h, s)
+    return s[:, 0], V[0], dV[:, 0], sA0[0], sA[:, 0]
+
+
+def _wrap(d):
+    return (d + np.pi) % (2 * np.pi) - np.pi
+
+
+def test_serving_with_deposits_matches_oracle(lib):
+    """Batched, evicting, depositing replay: every request checked against the oracle."""
+    spec, hills, wk, ctx = _setup(lib)
+    budget = 28 * int(wk.n_atoms.astype(np.int64).sum() // 3)     # about a third of the walkers fit
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=16, streams=2, deposit_every=3,
+                     height0=1.2, height_decay=20000.0, amplitude=AMP)
+    _register(srv, wk)
+    t, w, step = W.serving_requests(seed=1, n_walkers=N_WALKERS, rate=50_000.0, n_requests=600)
+    print(f"serving replay: {len(t)} requests, {N_WALKERS} walkers, budget {budget} B", flush=True)
+    out = srv.replay(w, step, t)
+    st = out["stats"]
+    n = len(t)
+    assert st["completed"] == n
+    assert st["evictions"] > 0 and st["admissions"] > N_WALKERS
+    assert st["max_batch_seen"] <= 16 and st["batches"] >= n // 16
+    assert np.all(np.isfinite(out["t_done"])) and np.all(out["t_done"] >= t)
+    # deposits: one per request whose step is a positive multiple of 3, slots dense after the seed hills
+    dep = out["deposit_slot"]
+    want_dep = (step % 3) == 0
+    assert np.array_equal(dep >= 0, want_dep)
+    slots = np.sort(dep[dep >= 0])
+    assert np.array_equal(slots, np.arange(N_HILLS, N_HILLS + slots.size))
+    assert ctx.num_hills == N_HILLS + slots.size == N_HILLS + st["deposits"]
+    # versions: seed hills at least, never a request's own deposit, non-decreasing per walker
+    ver = out["version"]
+    assert np.all(ver >= N_HILLS) and np.all(ver <= ctx.num_hills)
+    assert np.all(ver[dep >= 0] <= dep[dep >= 0])
+    for wi in range(N_WALKERS):
+        v = ver[w == wi]
+        assert np.all(np.diff(v) >= 0)
+    centers, heights = lib.abp_hills_export(ctx)
+    assert np.array_equal(centers[:, :N_HILLS], hills.centers)
+    # each deposited hill holds the depositing request's CV value and the height law's height
+    for r in np.flatnonzero(dep >= 0):
+        k = int(dep[r])
+        assert np.array_equal(centers[:, k], out["s"][:, r])
+        assert abs(heights[k] - 1.2 * np.exp(-k / 20000.0)) <= 1e-15 * heights[k]
+    # oracle re-evaluation of every request
+    s_g, V_g, dV_g = out["s"], out["V"], out["dVds"]
+    s_o = np.zeros_like(s_g); V_o = np.zeros_like(V_g); dV_o = np.zeros_like(dV_g)
+    A0 = np.zeros(n); A = np.zeros((wk.ncv, n))
+    for r in range(n):
+        s_o[:, r], V_o[r], dV_o[:, r], A0[r], A[:, r] = _oracle_request(
+            spec, centers, heights, wk, int(w[r]), int(step[r]), int(ver[r]))
+    assert np.abs(s_g[0] - s_o[0]).max() < 1e-12
+    assert np.abs(_wrap(s_g[1] - s_o[1])).max() < 1e-12
+    check_bound("served V", V_g, V_o, A0)
+    check_bound("served dVds", dV_g, dV_o, A)
+    srv.close()
+    ctx.close()
+
+
+def test_serving_alone_equals_in_the_mix(lib):
+    """Without deposits a request's result is bitwise the same whether it ran
+    alone (one request per launch, one stream) or inside mixed batches."""
+    spec, hills, wk, ctx = _setup(lib)
+    t, w, step = W.serving_requests(seed=2, n_walkers=N_WALKERS, rate=100_000.0, n_requests=400)
+    res = []
+    for mb, ns in ((1, 1), (64, 3)):
+        srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=mb, streams=ns, deposit_every=0,
+                         amplitude=AMP)
+        _register(srv, wk)
+        print(f"replay max_batch={mb} streams={ns}", flush=True)
+        res.append(srv.replay(w, step, t))
+        srv.close()
+    alone, mix = res
+    assert alone["stats"]["max_batch_seen"] == 1
+    assert mix["stats"]["batches"] < alone["stats"]["batches"]
+    for k in ("s", "V", "dVds"):
+        assert np.array_equal(alone[k], mix[k]), k
+    assert np.all(alone["version"] == N_HILLS) and np.all(mix["version"] == N_HILLS)
+    assert np.all(alone["deposit_slot"] == -1)
+    ctx.close()
+
+
+def test_serving_rejects_bad_input(lib):
+    spec, hills, wk, ctx = _setup(lib, n_hills=100, capacity_extra=16)
+    with pytest.raises(lib.AbpError):
+        lib.Server(ctx, [W.CV_TORSION, W.CV_TORSION])         # torsion on a non-periodic axis
+    with pytest.raises(lib.AbpError):
+        lib.Server(ctx, wk.kinds, max_batch=0)
+    small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=28 * 1000)
+    b, n = int(wk.atom_base[0]), int(wk.n_atoms[0])
+    lens, idx, rx, ry, rz = W.walker_lists(wk, 0)
+    with pytest.raises(lib.AbpError) as e:
+        small.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx)
+    assert e.value.status == lib.ABP_E_NOMEM
+    srv = lib.Server(ctx, wk.kinds)
+    bad = idx.copy()
+    bad[0] = n                                                 # out of range
+    with pytest.raises(lib.AbpError):
+        srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, bad)
+    wid = srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx)
+    with pytest.raises(lib.AbpError):
+        srv.replay([wid, wid], [1, 2], [0.001, 0.0])           # arrivals out of order
+    with pytest.raises(lib.AbpError):
+        srv.replay([wid, wid], [2, 2], [0.0, 0.0])             # steps must increase
+    with pytest.raises(lib.AbpError):
+        srv.replay([5], [1], [0.0])                            # unknown walker
+    out = srv.replay([wid], [1], [0.0])                        # still usable afterwards
+    assert out["stats"]["completed"] == 1
+    srv.close()
+    small.close()
+    ctx.close()
