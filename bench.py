@@ -30,6 +30,33 @@ VALU_LANE_OPS = CU * LANES * CLOCK     # non-packed VALU issue: 3.93e13 lane-ops
 # per axis: difference 1, minimum image 2, scale 1, square-accumulate 2,
 # gradient FMA 2; plus height multiply 1 and value add 1; the exp is not counted.
 FLOPS_PER_PAIR_2D = 18
+FP32_NONPACKED_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12   # FMA on every lane, no packed FP32: 78.6
+
+# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE (x 2,
+# copy-calibrated) and WRITE_SIZE (x 1), valid only for the kernel sources
+# they were taken on.
+HEADLINE_TRAFFIC = {"sources_sha256": "e9622e7fd45eb64a8ed447a3391b62a4a19b8d159ab098433c36d082eaf28943", "fetch_kib": 7298.8, "write_kib": 12288.0,
+                    "fetch_scale": 2.0, "write_scale": 1.0}
+HEADLINE_SOURCES = ("paper_1609_09833_amd/csrc/direct_sum_impl.h", "paper_1609_09833_amd/csrc/direct_sum_d2.hip",
+                    "paper_1609_09833_amd/csrc/direct_sum.hip", "paper_1609_09833_amd/csrc/abp_device.h",
+                    "paper_1609_09833_amd/csrc/abp_internal.h")
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def headline_traffic():
+    """Measured HBM bytes per launch, or None if the kernel changed since."""
+    t = HEADLINE_TRAFFIC
+    if sources_sha256(HEADLINE_SOURCES) != t["sources_sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
 def log(msg):
@@ -72,6 +99,37 @@ def cpu_baseline(spec, hills, q, target_s=15.0):
     return {"value": n / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} of {nq} queries (evenly spaced) against all {hills.n} hills, FP64, "
                       f"{dt:.1f} s"}
+
+
+def force_leg(abp, W, torch, args, stream):
+    """Fused bias force on 1024 walkers of 2,000-8,000 atoms (COM distance +
+    torsion), 20,000 hills: direct sum and grid, plus cv_compute alone."""
+    dev = torch.device("cuda", 0)
+    extra = {}
+    wk = W.ligand_pocket_walkers()
+    fspec, fhills = W.ligand_pocket_hills()
+    fctx = abp.Context(fspec, capacity=fhills.n)
+    abp.bias_deposit(fctx, torch.as_tensor(fhills.centers, device=dev), torch.as_tensor(fhills.heights, device=dev))
+    dw = abp.DeviceWalkers(wk, device=dev)
+    s_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
+    V_o = torch.empty(wk.nw, dtype=torch.float64, device=dev)
+    dV_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
+    for mode, name in ((abp.ABP_EVAL_DIRECT, "bias_force_direct"), (abp.ABP_EVAL_GRID, "bias_force_grid")):
+        def fstep(mode=mode):
+            abp.bias_force(fctx, dw, mode=mode, s=s_o, V=V_o, dVds=dV_o)
+        el4, _ = timed(fstep, args.steps, 2, stream)
+        extra[name] = {"walker_steps_per_s": wk.nw * args.steps / el4, "ms_per_step": el4 / args.steps * 1e3,
+                       "walkers": wk.nw, "hills": fhills.n}
+        log(f"bench: {name} {wk.nw * args.steps / el4:.4e} walker-steps/s")
+
+    def cstep():
+        abp.cv_compute(fctx, dw, s=s_o)
+    el5, _ = timed(cstep, args.steps, 2, stream)
+    extra["cv_compute"] = {"walker_steps_per_s": wk.nw * args.steps / el5, "ms_per_step": el5 / args.steps * 1e3}
+    log(f"bench: cv_compute {wk.nw * args.steps / el5:.4e} walker-steps/s")
+    abp.abp_sync(fctx)
+    fctx.close()
+    return extra
 
 
 def serving_leg(abp, W, torch, window_s=1.0):
@@ -157,6 +215,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
+    ap.add_argument("--only", choices=("headline", "force", "serving"), default=None,
+                    help="run one leg only (profiling): the headline direct sum, the fused bias-force "
+                         "workload, or the serving workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -172,6 +233,14 @@ def main():
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
+    if args.only_headline:
+        args.only = "headline"
+    if args.only == "force":
+        print(json.dumps({"extra": force_leg(abp, W, torch, args, stream)}), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps({"extra": {"serving": serving_leg(abp, W, torch)}}), flush=True)
+        return
     if args.calibrate_copy:
         n = 1 << 28                                   # 2^28 float32 = 1 GiB read + 1 GiB written per copy
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -222,12 +291,15 @@ def main():
                    "hills": nh, "queries_per_step": nq, "walkers": 1024, "steps_per_walker": 1024,
                    "sigma": [0.3, 0.3], "heights": "1.2*exp(-k/20000)", "query_io": "f32"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_direct_f32<2,3,GAUSS,2>", "pairs_per_s": pairs_s,
-                     "kernel_ms": ms_step},
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": headline_traffic(),
+                     "kernel": "k_direct_f32<2,3,GAUSS,ISO,KAHAN,2>", "pairs_per_s": pairs_s,
+                     "kernel_ms": ms_step, "flops_per_pair": FLOPS_PER_PAIR_2D,
+                     "peak_no_packed_fp32": FP32_NONPACKED_PEAK_TFLOPS,
+                     "frac_no_packed_fp32": achieved_tflops / FP32_NONPACKED_PEAK_TFLOPS},
     }
     log(f"bench: headline {value:.4e} walker-steps/s ({ms_step:.3f} ms/step, {pairs_s:.3e} pairs/s)")
-    if args.only_headline:
+    if args.only == "headline":
         print(json.dumps(out), flush=True)
         return
 
@@ -257,24 +329,7 @@ def main():
     extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
                           "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
     log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
-    # fused bias-force: 1024 walkers of 2,000-8,000 atoms, COM distance + torsion, 20,000 hills
-    wk = W.ligand_pocket_walkers()
-    fspec, fhills = W.ligand_pocket_hills()
-    fctx = abp.Context(fspec, capacity=fhills.n)
-    abp.bias_deposit(fctx, torch.as_tensor(fhills.centers, device=dev), torch.as_tensor(fhills.heights, device=dev))
-    dw = abp.DeviceWalkers(wk, device=dev)
-    s_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
-    V_o = torch.empty(wk.nw, dtype=torch.float64, device=dev)
-    dV_o = torch.empty((2, wk.nw), dtype=torch.float64, device=dev)
-    for mode, name in ((abp.ABP_EVAL_DIRECT, "bias_force_direct"), (abp.ABP_EVAL_GRID, "bias_force_grid")):
-        def fstep(mode=mode):
-            abp.bias_force(fctx, dw, mode=mode, s=s_o, V=V_o, dVds=dV_o)
-        el4, _ = timed(fstep, args.steps, 2, stream)
-        extra[name] = {"walker_steps_per_s": wk.nw * args.steps / el4, "ms_per_step": el4 / args.steps * 1e3,
-                       "walkers": wk.nw, "hills": fhills.n}
-        log(f"bench: {name} {wk.nw * args.steps / el4:.4e} walker-steps/s")
-    abp.abp_sync(fctx)
-    del fctx, dw
+    extra.update(force_leg(abp, W, torch, args, stream))
     if not args.no_serving:
         sv = serving_leg(abp, W, torch)
         head = sv["hist200k_budget512MiB"]

@@ -4,8 +4,8 @@
 // (section "Minimization of Interprocess Communications"): take the
 // coordinates of the CV atoms, compute the CVs, evaluate the bias gradient at
 // the CV value, and return forces on exactly those atoms, which are added to
-// the engine's forces. Here a batch of walkers does this in (at most) two
-// launches:
+// the engine's forces. Here a batch of walkers does this in three launches
+// (one with the grid form of the bias):
 //
 //   CV stage (one block per walker): one gather of every CV atom (index,
 //     position, mass) into registers; FP64 accumulators and a fixed-order
