@@ -129,7 +129,53 @@ def force_leg(abp, W, torch, args, stream):
     log(f"bench: cv_compute {wk.nw * args.steps / el5:.4e} walker-steps/s")
     abp.abp_sync(fctx)
     fctx.close()
+    extra["single_walker_latency"] = latency_leg(abp, W, torch)
     return extra
+
+
+def latency_leg(abp, W, torch, calls=200):
+    """One walker of 99,137 atoms with two 4-atom offset-RMSD CVs (the shape of
+    the paper's universal benchmark), mABP with compact hills (p = 20) on a
+    480 x 480 grid over [0, 12] nm: latency of one bias_force call, direct sum
+    at 3,000 and 100,000 hills and grid form."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    wk = W.rmsd_walkers(seed=2, n_walkers=1)
+    spec = W.BiasSpec(ndim=2, periodic=(0, 0), lo=(0.0, 0.0), hi=(12.0, 12.0), width=(0.25, 0.25),
+                      kernel=W.KERNEL_COMPACT, p=20, transform=W.TRANSFORM_MABP, kT=W.KT_300K, b=0.9, c=0.001,
+                      grid_n=(480, 480))
+    rng = np.random.default_rng(9)
+    dw = abp.DeviceWalkers(wk, device=dev)
+    s_o = torch.empty((2, 1), dtype=torch.float64, device=dev)
+    V_o = torch.empty(1, dtype=torch.float64, device=dev)
+    dV_o = torch.empty((2, 1), dtype=torch.float64, device=dev)
+    out = {"walker": "99,137 atoms, two 4-atom RMSD_OFF CVs", "calls": calls}
+    for n_hills in (3000, 100_000):
+        ctx = abp.Context(spec, capacity=n_hills)
+        cen = torch.as_tensor(rng.uniform(0.1, 0.4, (2, n_hills)), device=dev)
+        abp.bias_deposit(ctx, cen, torch.ones(n_hills, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        for mode, name in ((abp.ABP_EVAL_DIRECT, "direct"), (abp.ABP_EVAL_GRID, "grid")):
+            def call(mode=mode):
+                abp.bias_force(ctx, dw, mode=mode, s=s_o, V=V_o, dVds=dV_o)
+            for _ in range(10):
+                call()
+            torch.cuda.synchronize()
+            lat = np.empty(calls)
+            for i in range(calls):
+                t0 = time.perf_counter()
+                call()
+                torch.cuda.synchronize()
+                lat[i] = time.perf_counter() - t0
+            el, _ = timed(call, calls, 0, torch.cuda.current_stream())
+            key = f"{name}_{n_hills}_hills"
+            out[key] = {"p50_us": float(np.percentile(lat, 50) * 1e6), "p99_us": float(np.percentile(lat, 99) * 1e6),
+                        "back_to_back_us": el / calls * 1e6}
+            log(f"bench: single walker {key}: p50 {out[key]['p50_us']:.1f} us, back-to-back "
+                f"{out[key]['back_to_back_us']:.1f} us per call")
+        abp.abp_sync(ctx)
+        ctx.close()
+    return out
 
 
 def serving_leg(abp, W, torch, window_s=1.0):
@@ -191,6 +237,7 @@ def serving_leg(abp, W, torch, window_s=1.0):
     n_win = int(rate * window_s)
     budget = 512 << 20
     srv = server(budget, 1024, 3)
+    run(srv, "warm-up (not reported)", n_win // 5, 99)     # first launches, cold pool
     for i, hist in enumerate((0, 100_000, 200_000)):
         seed_to(hist)
         res[f"hist{hist // 1000}k_budget512MiB"] = run(srv, f"{hist} hills, 512 MiB", n_win, 100 + i)

@@ -182,10 +182,15 @@ abp_status bias_eval(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, int64_t nq
 abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* walkers, double* s,
                       abp_stream stream);
 
-/* The whole bias-force step for a batch of walkers, one fused launch:
- * CVs -> bias and gradient at s (DIRECT: hills [0, n_visible[w]), or all
- * committed hills if n_visible is NULL; GRID: interpolation) -> transform ->
- * chain rule F_j += -sum_a dV/ds_a ds_a/dx_j on the CV atoms only.
+/* The whole bias-force step for a batch of walkers: CVs -> bias and
+ * gradient at s (DIRECT: hills [0, n_visible[w]), or all committed hills if
+ * n_visible is NULL; GRID: interpolation) -> transform -> chain rule
+ * F_j += -sum_a dV/ds_a ds_a/dx_j on the CV atoms only ("Minimization of
+ * Interprocess Communications": only CV atoms are read and written).
+ * One launch for the grid form and for histories of up to 16,384 hills,
+ * three launches (CV, hill sum, finish) for longer ones; the environment
+ * variable ABP_FORCE_SHAPE=fused|split forces one or the other. A walker's
+ * result is bitwise the same in any batch and either shape.
  * Writes s[ncv][nw], V[nw], dVds[ncv][nw] (FP64).
  * deposit_slot (optional, [nw]): if deposit_slot[w] >= 0, the hill centred at
  * walker w's s with height deposit_height[w] (NULL: 1.0) is written to that

@@ -261,9 +261,9 @@ __device__ __forceinline__ void hermite_eval(const Consts& K, const double* __re
 // ---------------------------------------------------------------------------
 // Block-wide FP64 sum in a fixed order (wave butterfly, then waves in order).
 // All threads of the block must call it; every thread gets the total.
-// `red` is LDS scratch of at least kBlock/64 * N doubles.
+// `red` is LDS scratch of at least NT/64 * N doubles (NT threads in the block).
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int NT = kBlock>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 #pragma unroll
   for (int r = 0; r < N; ++r) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
 #pragma unroll
   for (int r = 0; r < N; ++r) {
     double t = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) t += red[w * N + r];
+    for (int w = 0; w < NT / 64; ++w) t += red[w * N + r];
     v[r] = t;
   }
   __syncthreads();

@@ -405,7 +405,7 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
   A.use_grid = mode == ABP_EVAL_GRID ? 1 : 0;
   A.grid = ctx->grid;
   A.prec = prec;
-  if (!A.use_grid) {
+  if (abp::force_uses_workspace(walkers->nw, ctx->committed, A.use_grid, 0)) {
     const int nbw = abp::force_blocks_per_walker(ctx->committed, 0, 0);
     st = force_workspace(ctx, walkers->nw, nbw);
     if (st != ABP_OK) return st;

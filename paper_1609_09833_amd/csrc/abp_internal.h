@@ -116,13 +116,17 @@ struct ForceArgs {
   int32_t* err;
 };
 
-// Hills per chunk of a walker's sum in bias_force (one lane sums one chunk).
-// Fixed, so the split of a walker's sum never depends on the batch it is in.
-constexpr int kHillsPerBlock = 256;
+// A walker's direct sum in bias_force over nvis hills is split into chunks of
+// kChunkHills consecutive hills (a function of nvis alone), so the split never
+// depends on the batch the walker is in.
+constexpr int kChunkHills = 64;
+__host__ __device__ inline int64_t force_chunks(int64_t nvis) { return (nvis + kChunkHills - 1) / kChunkHills; }
 
-// Chunks per walker of the sum stage, and the workspace bytes a direct-sum
-// bias_force launch needs (CV state, cached atom lists, chunk partials).
+// Chunk partials per walker for a history of `committed` hills; whether a
+// launch of nw walkers takes the split shape (which needs the workspace); the
+// workspace bytes of that shape (CV state, cached atom lists, partials).
 int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only);
+bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only);
 size_t force_workspace_bytes(int64_t nw, int nbw, int ndim);
 hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* workspace,
                              hipStream_t stream);

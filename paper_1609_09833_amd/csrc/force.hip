@@ -4,33 +4,41 @@
 // (section "Minimization of Interprocess Communications"): take the
 // coordinates of the CV atoms, compute the CVs, evaluate the bias gradient at
 // the CV value, and return forces on exactly those atoms, which are added to
-// the engine's forces. Here a batch of walkers does this in three launches
-// (one with the grid form of the bias):
+// the engine's forces.
 //
-//   CV stage (one block per walker): one gather of every CV atom (index,
-//     position, mass) into registers; FP64 accumulators and a fixed-order
-//     block reduction for centres of mass; the dihedral angle; the offset
-//     RMSD of section "Definition of the RMSD". With the grid form of the
-//     bias this block also interpolates, transforms and applies the forces.
-//     With the direct sum it hands the CV state and the atom list over to:
-//   Sum stage (waves of 64 walkers x chunks of kHillsPerBlock hills): each
-//     lane sums one chunk of hills at its walker's CV value, in index order
-//     (FP32 terms folded into Kahan sums every 32 hills, or FP64). Hill
-//     records are wave-uniform scalar loads, fetched once per 64 walkers.
-//   Finish stage (one block per walker): merges the chunk partials in a fixed
-//     order with error-free FP32 TwoSum steps (or FP64), then transform
-//     (eq. apfm / eq. btraj-grad), outputs, deposit and chain rule. Chunk
-//     boundaries depend only on n_visible[w], so a walker's result is
-//     bitwise the same alone or in any batch; no block waits for another and
-//     no atomics or device-wide fences are used.
-//   Chain rule: F_j += -sum_a dV/ds_a ds_a/dx_j. When the COM/RMSD lists are
-//     disjoint and short (the usual ligand/pocket case), every atom's total is
-//     formed once and written once (a torsion atom that is also a ligand atom
-//     is folded into that ligand entry); otherwise lists are applied one after
-//     another with a barrier between them. Either way the sum per atom has a
-//     fixed order and no atomics touch the forces.
-//   Optional: write a new hill centred at the walker's CV value into a
-//     reserved history slot (the deposit of eq. update at this step).
+// CV part (one 128-thread block per walker): one gather of every CV atom
+// (index, position, mass); FP64 accumulators and a fixed-order block
+// reduction for centres of mass; the dihedral angle; the offset RMSD of
+// section "Definition of the RMSD".
+//
+// Bias from the hill history (direct sum). A walker's sum over its visible
+// hills [0, nvis) always has the same decomposition: chunks of 64
+// consecutive hills, each summed in increasing order (FP32 terms folded into
+// a Kahan sum every 32 terms, or FP64); thread t of a 128-thread block merges
+// chunks t, t + 128, ... in that order (error-free FP32 TwoSum steps, or FP64
+// adds), then a fixed block tree merges the threads. Two launch shapes
+// compute exactly this:
+//   fused (a short history): one launch, the walker's block does the CV
+//     part, sums its own chunks and finishes;
+//   split (a long history): a CV launch, a sum launch of one wave per
+//     (chunk, 64 walkers) in which every lane sums the chunk at its walker's
+//     CV value with the hill records read as wave-uniform scalar loads (each
+//     fetched once per 64 walkers), and a finish launch that merges the
+//     chunk sums.
+// So a walker's result is bitwise the same alone or in any batch, whichever
+// shape runs. No block waits for another; no atomics touch sums or forces.
+//
+// Finish: transform (eq. apfm / eq. btraj-grad), outputs, optional deposit of
+// a hill at the walker's CV value into a reserved slot (eq. update), and the
+// chain rule F_j += -sum_a dV/ds_a ds_a/dx_j. When the COM/RMSD lists are
+// disjoint and short (the usual ligand/pocket case), every atom's total is
+// formed once and written once (a torsion atom that is also a ligand atom is
+// folded into that ligand entry); otherwise lists are applied one after
+// another with a barrier between them. Either way the sum per atom has a
+// fixed order. With the grid form of the bias the CV block interpolates,
+// transforms and finishes in the same launch.
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "abp_device.h"
@@ -38,14 +46,23 @@
 namespace abp {
 namespace {
 
-constexpr int kCache = 4;               // CV-list entries per thread kept in registers
-constexpr int kMaxCached = kCache * kBlock;
+// Threads per walker block. Two waves: at the CV part's register footprint
+// (about 150 VGPRs, 3 waves per SIMD) a CU holds 6 walker blocks, so 1,024
+// walkers are resident at once.
+constexpr int kFBlock = 128;
+constexpr int kCache = 6;               // CV-list entries per thread kept in registers
+constexpr int kMaxCached = kCache * kFBlock;
 constexpr int kMaxTors = 3;             // torsion CVs (one per axis at most)
 constexpr double kMinDist = 1e-12;      // below this COM distance the direction is undefined
 constexpr double kMinCross2 = 1e-24;    // collinear torsion atoms
 
+// Histories up to this length use the fused launch; longer ones the split
+// launches, whose sum launch reads each hill record once per 64 walkers
+// instead of once per walker (the result does not depend on the choice).
+constexpr int64_t kFusedMaxHills = 16384;
+
 // CV state of one walker, held in LDS by a block and in the workspace
-// between the two stages.
+// between the launches of the split shape.
 struct CvState {
   double s[3];
   double cv[3][12];        // COM: u(3), 1/M_A, 1/M_B; TORSION: gradient (12); RMSD: 1/(N r)
@@ -69,10 +86,11 @@ struct FArgs {
   HistView H;
   ForceArgs A;
   int64_t committed;
-  int32_t nbw;                 // sum-stage blocks per walker in the grid (upper bound)
-  CvState* state;              // [nw]
-  Entry* entries;              // [nw][kMaxCached]
-  double2* partials;           // [nw][nbw][D+1] (hi, lo) per block
+  int32_t pmax;                // chunk partials per walker in the workspace (for nvis = committed)
+  CvState* state;              // [nw]                 split shape only
+  Entry* entries;              // [nw][kMaxCached]     split shape only
+  float2* part32;              // [nw][pmax][D+1] partial sums (hi, lo), FP32 modes
+  double* part64;              // the same buffer, FP64 mode
 };
 
 __device__ __forceinline__ void list_bounds(const ForceArgs& A, int64_t w, int q, int& b, int& n) {
@@ -84,6 +102,17 @@ __device__ __forceinline__ void list_bounds(const ForceArgs& A, int64_t w, int q
     b = off[w];
     n = off[w + 1] - off[w];
   }
+}
+
+__device__ __forceinline__ int64_t walker_nvis(const FArgs& F, int64_t w) {
+  int64_t nvis = F.A.n_visible ? F.A.n_visible[w] : F.A.n_visible_default;
+  return (nvis < 0 || nvis > F.committed) ? F.committed : nvis;
+}
+
+// Hills of chunk c that lie below nvis.
+__device__ __forceinline__ int chunk_terms(int64_t nvis, int64_t c) {
+  const int64_t n = nvis - c * kChunkHills;
+  return n <= 0 ? 0 : (n >= kChunkHills ? kChunkHills : (int)n);
 }
 
 // ---- compensated FP32 pairs: value = hi + lo ------------------------------
@@ -109,7 +138,7 @@ __device__ __forceinline__ void merge_f32(float (&h)[N], float (&l)[N], const fl
 
 // Block-wide merge in a fixed tree: wave butterfly (the merge is commutative,
 // so every lane ends with the same value), then waves 0..3 in order. Every
-// thread gets the result. `red` holds at least kBlock/64 * N * 2 floats.
+// thread gets the result. `red` holds at least kFBlock/64 * N * 2 floats.
 template <int N>
 __device__ __forceinline__ void block_merge_f32(float (&h)[N], float (&l)[N], bool comp, float* red) {
 #pragma unroll
@@ -134,7 +163,7 @@ __device__ __forceinline__ void block_merge_f32(float (&h)[N], float (&l)[N], bo
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < N; ++r) { h[r] = red[r * 2]; l[r] = red[r * 2 + 1]; }
-  for (int wv = 1; wv < kBlock / 64; ++wv) {
+  for (int wv = 1; wv < kFBlock / 64; ++wv) {
     float h2[N], l2[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) { h2[r] = red[(wv * N + r) * 2]; l2[r] = red[(wv * N + r) * 2 + 1]; }
@@ -263,7 +292,7 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
       for (int t = 0; t < 2; ++t) {
         const double scale = t == 0 ? -g * S.cv[a][3] : g * S.cv[a][4];
         const int b0 = S.lb[2 * a + t], n = S.ln[2 * a + t];
-        for (int e = b0 + tid; e < b0 + n; e += kBlock) {
+        for (int e = b0 + tid; e < b0 + n; e += kFBlock) {
           const int64_t gi = base + A.list_idx[e];
           const double c = scale * (double)A.mass[gi];
           rmw_force(A.fx, gi, c * ux);
@@ -283,7 +312,7 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
     } else {
       const double c = -g * S.cv[a][0];
       const int b0 = S.lb[2 * a], n = S.ln[2 * a];
-      for (int e = b0 + tid; e < b0 + n; e += kBlock) {
+      for (int e = b0 + tid; e < b0 + n; e += kFBlock) {
         const int64_t gi = base + A.list_idx[e];
         rmw_force(A.fx, gi, c * ((double)A.x[gi] - (double)A.ref_x[e]));
         rmw_force(A.fy, gi, c * ((double)A.y[gi] - (double)A.ref_y[e]));
@@ -294,22 +323,18 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
   }
 }
 
-enum { kStageCV = 0, kStageGrid = 1, kStageSum = 2 };
-
-// ---------------------------------------------------------------------------
-// CV stage: one block per walker.
-// ---------------------------------------------------------------------------
-template <int D, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
+// CV part of the step for walker w (all threads of the block): validates the
+// lists, gathers every CV atom once (the first kMaxCached entries are kept in
+// `ent`), reduces the centres of mass and RMSD sums in FP64, and thread 0
+// forms the CVs and their gradients in S. Returns false when the walker is
+// done: invalid (the error word is set, and F.state[w].bad when to_state) or
+// cv_only (s written). Otherwise S.fast tells whether the one-pass chain rule
+// applies (no atom in two COM/RMSD lists).
+template <int D>
+__device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state, CvState& S,
+                         Entry (&ent)[kCache], double* red, double (&tpos)[kMaxTors][4][3], int* sh_list) {
   const ForceArgs& A = F.A;
-  const Consts& K = F.K;
-  const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
-  __shared__ double red[(kBlock / 64) * (9 * D + 1)];
-  __shared__ CvState S;
-  __shared__ double tpos[kMaxTors][4][3];
-  __shared__ int sh_list[kMaxCached];     // atom index per position in the concatenated lists
-
   const int64_t base = A.atom_base[w];
   const int32_t natoms = A.n_atoms[w];
   if (tid == 0) {
@@ -343,9 +368,9 @@ __global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
   if (S.bad) {
     if (tid == 0) {
       atomicOr(A.err, S.bad);
-      if (STAGE == kStageSum) F.state[w].bad = S.bad;
+      if (to_state) F.state[w].bad = S.bad;
     }
-    return;
+    return false;
   }
   const int total = S.total;
 
@@ -355,7 +380,6 @@ __global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
   double acc[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
-  Entry ent[kCache];
   int badbits = 0;
   // Register arrays are only indexed with compile-time constants (dynamic
   // indices would move them to scratch memory).
@@ -401,26 +425,26 @@ __global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
   };
 #pragma unroll
   for (int k = 0; k < kCache; ++k) {
-    const int r = k * kBlock + tid;
+    const int r = k * kFBlock + tid;
     ent[k].gi = -1;
     ent[k].li = 0;
     ent[k].e = 0;
     ent[k].m = 0.0f;
     if (r < total) gather(r, ent[k]);
   }
-  for (int r = kMaxCached + tid; r < total; r += kBlock) {
+  for (int r = kMaxCached + tid; r < total; r += kFBlock) {
     Entry tmp;
     gather(r, tmp);
   }
   if (badbits) atomicOr(&S.bad, badbits);
   acc[9 * D] = badbits ? 1.0 : 0.0;
-  block_sum<NACC>(acc, red);          // its barriers also publish S.bad, tpos and the torsion atoms
+  block_sum<NACC, kFBlock>(acc, red);          // its barriers also publish S.bad, tpos and the torsion atoms
   if (acc[9 * D] != 0.0) {
     if (tid == 0) {
       atomicOr(A.err, S.bad ? S.bad : kErrIndex);
-      if (STAGE == kStageSum) F.state[w].bad = S.bad ? S.bad : kErrIndex;
+      if (to_state) F.state[w].bad = S.bad ? S.bad : kErrIndex;
     }
-    return;
+    return false;
   }
 
   // ---- CV values (thread 0)
@@ -502,14 +526,14 @@ __global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
   if (S.bad) {
     if (tid == 0) {
       atomicOr(A.err, S.bad);
-      if (STAGE == kStageSum) F.state[w].bad = S.bad;
+      if (to_state) F.state[w].bad = S.bad;
     }
-    return;
+    return false;
   }
-  if (STAGE == kStageCV) {
+  if (cv_only) {
     if (tid == 0)
       for (int a = 0; a < D; ++a) A.s[a * A.nw + w] = S.s[a];
-    return;
+    return false;
   }
 
   // ---- fast chain-rule path possible? (no atom in two COM/RMSD lists)
@@ -535,44 +559,97 @@ __global__ __launch_bounds__(kBlock) void k_cv_stage(const FArgs F) {
     if (dup) atomicAnd(&S.fast, 0);
     __syncthreads();
   }
-
-  if (STAGE == kStageSum) {
-    // hand the CV state and the cached entries to the sum stage
-    const int* src = reinterpret_cast<const int*>(&S);
-    int* dst = reinterpret_cast<int*>(F.state + w);
-    for (int i = tid; i < kStateWords; i += kBlock) dst[i] = src[i];
-    Entry* out = F.entries + w * (int64_t)kMaxCached;
-#pragma unroll
-    for (int k = 0; k < kCache; ++k)
-      if (k * kBlock + tid < total) out[k * kBlock + tid] = ent[k];
-    return;
-  }
-
-  // ---- grid form: interpolate, transform, forces (this block does it all)
-  double s[D], h, dh[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) s[a] = S.s[a];
-  bool clamped;
-  hermite_eval<D>(K, A.grid, s, h, dh, clamped);   // every thread, same result
-  double V, dV[D];
-  apply_transform<D>(K, h, dh, V, dV);
-  __syncthreads();
-  if (tid == 0) {
-    for (int a = 0; a < D; ++a) S.dV[a] = dV[a];
-    write_outputs<D>(F, w, S, V);
-  }
-  __syncthreads();
-  apply_forces<D>(A, base, S, ent);
+  return true;
 }
 
-// Merged sums -> transform -> outputs, deposit, chain rule (one block per walker).
-template <int D, bool FP64>
-__device__ void finish_walker(const FArgs& F, int64_t w, const float (&hi)[D + 1], const float (&lo)[D + 1],
-                              const double (&v64)[D + 1], CvState& S) {
+// ---------------------------------------------------------------------------
+// One chunk sum (FP32): hills k0, k0 + 1, ... for nrun terms; terms from
+// nmine on are zero-height (MASK) and the Kahan folds of groups that end past
+// nmine are skipped, which gives exactly the sum of nmine terms.
+// `load(k)` returns hill k's FP32 record.
+// ---------------------------------------------------------------------------
+template <int D, int PMASK, int KERN, bool MASK, class Load>
+__device__ __forceinline__ void partial_f32(const uint32_t (&qw)[D], const float (&kf)[D], const float (&ua)[D],
+                                            float pl, bool comp, int64_t k0, int nrun, int nmine, Load load,
+                                            float (&hi)[D + 1], float (&lo)[D + 1]) {
   constexpr int N = D + 1;
-  const ForceArgs& A = F.A;
+  float Sm[N], Cc[N], Pp[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) { Sm[r] = 0.0f; Cc[r] = 0.0f; Pp[r] = 0.0f; }
+  const int ninf = __float_as_int(-__builtin_inff());
+  int u = 0;
+  for (; u + 32 <= nrun; u += 32) {
+#pragma unroll 8
+    for (int j = 0; j < 32; ++j) {
+      int4 h = load(k0 + u + j);
+      if (MASK && u + j >= nmine) h.w = ninf;
+      pair32<D, PMASK, KERN>(qw, h, kf, ua, pl, Pp);
+    }
+    if (comp && (!MASK || u + 32 <= nmine)) {
+      kahan_fold<N>(Sm, Cc, Pp);
+#pragma unroll
+      for (int r = 0; r < N; ++r) Pp[r] = 0.0f;
+    }
+  }
+  for (; u < nrun; ++u) {
+    int4 h = load(k0 + u);
+    if (MASK && u >= nmine) h.w = ninf;
+    pair32<D, PMASK, KERN>(qw, h, kf, ua, pl, Pp);
+  }
+  if (comp) {
+    kahan_fold<N>(Sm, Cc, Pp);
+#pragma unroll
+    for (int r = 0; r < N; ++r) { hi[r] = Sm[r]; lo[r] = -Cc[r]; }
+  } else {
+#pragma unroll
+    for (int r = 0; r < N; ++r) { hi[r] = Pp[r]; lo[r] = 0.0f; }
+  }
+}
+
+// One chunk sum (FP64), same terms; zero-height terms add exact zeros.
+template <int D, int KERN, bool MASK, class Load>
+__device__ __forceinline__ void partial_f64(const Consts& K, const double (&tq)[D], int64_t k0, int nrun,
+                                            int nmine, Load load, double (&v)[D + 1]) {
+  double Pp[D + 1];
+#pragma unroll
+  for (int r = 0; r <= D; ++r) Pp[r] = 0.0;
+  for (int u = 0; u < nrun; ++u) {
+    double4 hr = load(k0 + u);
+    if (MASK && u >= nmine) hr.w = 0.0;
+    pair64<D, KERN>(K, tq, hr, Pp);
+  }
+#pragma unroll
+  for (int r = 0; r <= D; ++r) v[r] = Pp[r];
+}
+
+__device__ __forceinline__ double4 hill64(const FArgs& F, int D, int64_t k) {
+  double4 hr;
+  hr.x = work64(F.K, 0, F.H.c64[k]);
+  hr.y = D > 1 ? work64(F.K, 1, F.H.c64[F.H.capacity + k]) : 0.0;
+  hr.z = D > 2 ? work64(F.K, 2, F.H.c64[2 * F.H.capacity + k]) : 0.0;
+  hr.w = F.H.w64[k];
+  return hr;
+}
+
+// Merge one partial into a thread's running (hi, lo) or FP64 sum.
+template <int N, bool FP64>
+__device__ __forceinline__ void merge_part(float (&hi)[N], float (&lo)[N], double (&v64)[N], const float (&ph)[N],
+                                           const float (&pl)[N], const double (&pv)[N], bool comp) {
+  if (FP64) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) v64[r] += pv[r];
+  } else {
+    merge_f32<N>(hi, lo, ph, pl, comp);
+  }
+}
+
+// Merged sums -> transform -> outputs, deposit, chain rule (all threads; S
+// and ent hold the walker's CV state and cached entries).
+template <int D, bool FP64>
+__device__ void finish_common(const FArgs& F, int64_t w, const float (&hi)[D + 1], const float (&lo)[D + 1],
+                              const double (&v64)[D + 1], CvState& S, const Entry (&ent)[kCache]) {
+  constexpr int N = D + 1;
   const Consts& K = F.K;
-  const int tid = threadIdx.x;
   double tot[N];
 #pragma unroll
   for (int r = 0; r < N; ++r) tot[r] = FP64 ? v64[r] : (double)hi[r] + (double)lo[r];
@@ -581,79 +658,156 @@ __device__ void finish_walker(const FArgs& F, int64_t w, const float (&hi)[D + 1
   for (int i = 0; i < D; ++i) dh[i] = tot[i + 1] * (FP64 ? K.gs64[i] : K.gs32[i]);
   double V, dV[D];
   apply_transform<D>(K, tot[0], dh, V, dV);
-
-  // ---- outputs, deposit, chain rule
-  {
-    const int* src = reinterpret_cast<const int*>(F.state + w);
-    int* dst = reinterpret_cast<int*>(&S);
-    for (int i = tid; i < kStateWords; i += kBlock) dst[i] = src[i];
-  }
-  Entry ent[kCache];
-  const Entry* in = F.entries + w * (int64_t)kMaxCached;
-  const int total = F.state[w].total;
-#pragma unroll
-  for (int k = 0; k < kCache; ++k) {
-    ent[k].gi = -1;
-    ent[k].li = 0;
-    ent[k].e = 0;
-    ent[k].m = 0.0f;
-    if (k * kBlock + tid < total) ent[k] = in[k * kBlock + tid];
-  }
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     for (int a = 0; a < D; ++a) S.dV[a] = dV[a];
     write_outputs<D>(F, w, S, V);
   }
   __syncthreads();
-  apply_forces<D>(A, A.atom_base[w], S, ent);
+  apply_forces<D>(F.A, F.A.atom_base[w], S, ent);
 }
 
+// ---------------------------------------------------------------------------
+// CV launch: cv_compute (STAGE kStageCV), the whole grid-form step
+// (kStageGrid), or the first launch of the split shape (kStageSum: hands the
+// CV state and the cached entries to the workspace).
+// ---------------------------------------------------------------------------
+enum { kStageCV = 0, kStageGrid = 1, kStageSum = 2 };
+
+template <int D, int STAGE>
+__global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
+  const ForceArgs& A = F.A;
+  const int64_t w = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double red[(kFBlock / 64) * (9 * D + 1)];
+  __shared__ CvState S;
+  __shared__ double tpos[kMaxTors][4][3];
+  __shared__ int sh_list[kMaxCached];
+  Entry ent[kCache];
+  if (!cv_block<D>(F, w, STAGE == kStageCV, STAGE == kStageSum, S, ent, red, tpos, sh_list)) return;
+
+  if (STAGE == kStageSum) {
+    const int* src = reinterpret_cast<const int*>(&S);
+    int* dst = reinterpret_cast<int*>(F.state + w);
+    for (int i = tid; i < kStateWords; i += kFBlock) dst[i] = src[i];
+    Entry* out = F.entries + w * (int64_t)kMaxCached;
+#pragma unroll
+    for (int k = 0; k < kCache; ++k)
+      if (k * kFBlock + tid < S.total) out[k * kFBlock + tid] = ent[k];
+    return;
+  }
+  if constexpr (STAGE == kStageGrid) {
+    double s[D], h, dh[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) s[a] = S.s[a];
+    bool clamped;
+    hermite_eval<D>(F.K, A.grid, s, h, dh, clamped);   // every thread, same result
+    double V, dV[D];
+    apply_transform<D>(F.K, h, dh, V, dV);
+    __syncthreads();
+    if (tid == 0) {
+      for (int a = 0; a < D; ++a) S.dV[a] = dV[a];
+      write_outputs<D>(F, w, S, V);
+    }
+    __syncthreads();
+    apply_forces<D>(A, A.atom_base[w], S, ent);
+  }
+}
 
 // ---------------------------------------------------------------------------
-// Sum stage: one wave per (tile of 64 walkers, chunk of kHillsPerBlock hills).
-// Each lane sums the chunk's hills at its walker's CV value in index order;
-// hill records are wave-uniform and arrive through the scalar cache, so each
-// record is fetched once per 64 walkers. The lane's compensated partial is
-// stored per (walker, chunk).
+// Fused shape: the whole direct-sum step of one walker in one block.
 // ---------------------------------------------------------------------------
 template <int D, int PMASK, int KERN, bool FP64>
-__global__ __launch_bounds__(64) void k_sum_tiles(const FArgs F) {
+__global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
+  constexpr int N = D + 1;
+  const ForceArgs& A = F.A;
+  const Consts& K = F.K;
+  const int64_t w = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double red[(kFBlock / 64) * (9 * D + 1)];
+  __shared__ CvState S;
+  __shared__ double tpos[kMaxTors][4][3];
+  __shared__ int sh_list[kMaxCached];
+  Entry ent[kCache];
+  if (!cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list)) return;
+
+  const int64_t nvis = walker_nvis(F, w);
+  const int64_t nch = force_chunks(nvis);
+  float hi[N], lo[N];
+  double v64[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) { hi[r] = 0.0f; lo[r] = 0.0f; v64[r] = 0.0; }
+  const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
+  if constexpr (FP64) {
+    double tq[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) tq[i] = work64(K, i, S.s[i]);
+    for (int64_t c = tid; c < nch; c += kFBlock) {
+      const int n = chunk_terms(nvis, c);
+      double pv[N];
+      partial_f64<D, KERN, false>(K, tq, c * kChunkHills, n, n, [&](int64_t k) { return hill64(F, D, k); }, pv);
+      const float z[N] = {};
+      merge_part<N, true>(hi, lo, v64, z, z, pv, comp);
+    }
+    block_sum<N, kFBlock>(v64, red);
+  } else {
+    uint32_t qw[D];
+    float kf[D], ua[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      qw[i] = work32(K, i, S.s[i]);
+      kf[i] = K.kf32[i];
+      ua[i] = K.ua32[i];
+    }
+    const int4* recs = F.H.rec32;
+    for (int64_t c = tid; c < nch; c += kFBlock) {
+      const int n = chunk_terms(nvis, c);
+      float ph[N], pl[N];
+      partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, c * kChunkHills, n, n,
+                                         [&](int64_t k) { return recs[k]; }, ph, pl);
+      const double z[N] = {};
+      merge_part<N, false>(hi, lo, v64, ph, pl, z, comp);
+    }
+    block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
+  }
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+}
+
+// ---------------------------------------------------------------------------
+// Split shape, sum launch: one wave per (chunk c, 64 walkers). The chunk's
+// hill indices are wave-uniform, so the records come through the scalar
+// cache, fetched once per 64 walkers; a lane whose walker sees fewer hills
+// masks the rest.
+// ---------------------------------------------------------------------------
+template <int D, int PMASK, int KERN, bool FP64>
+__global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const Consts& K = F.K;
   const int lane = threadIdx.x;
-  const int64_t w = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t c = blockIdx.y;
+  const int64_t c = blockIdx.x;
+  const int64_t w = (int64_t)blockIdx.y * 64 + lane;
   const bool active = w < A.nw;
   const int64_t wc = active ? w : A.nw - 1;
-  int64_t nvis = A.n_visible ? A.n_visible[wc] : A.n_visible_default;
-  if (nvis < 0 || nvis > F.committed) nvis = F.committed;
-  const int64_t k0 = c * kHillsPerBlock;
-  const int64_t kmax = k0 + kHillsPerBlock < F.committed ? k0 + kHillsPerBlock : F.committed;   // uniform
-  const int64_t kstop = kmax < nvis ? kmax : nvis;                                                // per lane
-  const bool wanted = active && k0 < nvis && !F.state[wc].bad;
+  const int64_t nvis = walker_nvis(F, wc);
+  const bool wanted = active && c * kChunkHills < nvis && !F.state[wc].bad;
   if (!__any(wanted)) return;
-  const bool full = __all(!wanted || kstop == kmax) != 0;
+  const int nmine = wanted ? chunk_terms(nvis, c) : 0;
+  const int nrun = chunk_terms(F.committed, c);                 // uniform, >= nmine
+  const bool full = __all(!wanted || nmine == nrun);
+  const int64_t k0 = c * kChunkHills;
   double s[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) s[a] = F.state[wc].s[a];
-  double2 out[N];
+  float ph[N], pl[N];
+  double pv[N];
   if constexpr (FP64) {
-    double tq[D], P[N];
+    double tq[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) tq[i] = work64(K, i, s[i]);
-#pragma unroll
-    for (int r = 0; r < N; ++r) P[r] = 0.0;
-    for (int64_t k = k0; k < kmax; ++k) {
-      double4 hr;
-      hr.x = work64(K, 0, F.H.c64[k]);
-      hr.y = D > 1 ? work64(K, 1, F.H.c64[F.H.capacity + k]) : 0.0;
-      hr.z = D > 2 ? work64(K, 2, F.H.c64[2 * F.H.capacity + k]) : 0.0;
-      hr.w = (full || k < kstop) ? F.H.w64[k] : 0.0;
-      pair64<D, KERN>(K, tq, hr, P);
-    }
-#pragma unroll
-    for (int r = 0; r < N; ++r) { out[r].x = P[r]; out[r].y = 0.0; }
+    auto ld = [&](int64_t k) { return hill64(F, D, k); };
+    if (full) partial_f64<D, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
+    else partial_f64<D, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
   } else {
     uint32_t qw[D];
     float kf[D], ua[D];
@@ -664,166 +818,166 @@ __global__ __launch_bounds__(64) void k_sum_tiles(const FArgs F) {
       ua[i] = K.ua32[i];
     }
     const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
-    typedef const __attribute__((address_space(4))) int cint4_t;   // uniform loads via the scalar cache
-    cint4_t* recs = (cint4_t*)F.H.rec32;
-    float Sm[N], Cc[N], P[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) { Sm[r] = 0.0f; Cc[r] = 0.0f; P[r] = 0.0f; }
-    const float ninf = -__builtin_inff();
-    // MASK: some lanes stop before kmax (their walker sees fewer hills).
-    auto run = [&](auto mask_tag) {
-      constexpr bool MASK = decltype(mask_tag)::value;
-      int64_t k = k0;
-      for (; k + 32 <= kmax; k += 32) {
-#pragma unroll 8
-        for (int u = 0; u < 32; ++u) {
-          int4 h;
-          h.x = recs[4 * (k + u)];
-          h.y = D > 1 ? recs[4 * (k + u) + 1] : 0;
-          h.z = D > 2 ? recs[4 * (k + u) + 2] : 0;
-          h.w = recs[4 * (k + u) + 3];
-          if (MASK && k + u >= kstop) h.w = __float_as_int(ninf);
-          pair32<D, PMASK, KERN>(qw, h, kf, ua, K.pl32, P);
-        }
-        if (comp) {
-          kahan_fold<N>(Sm, Cc, P);
-#pragma unroll
-          for (int r = 0; r < N; ++r) P[r] = 0.0f;
-        }
-      }
-      for (; k < kmax; ++k) {
-        int4 h;
-        h.x = recs[4 * k];
-        h.y = D > 1 ? recs[4 * k + 1] : 0;
-        h.z = D > 2 ? recs[4 * k + 2] : 0;
-        h.w = recs[4 * k + 3];
-        if (MASK && k >= kstop) h.w = __float_as_int(ninf);
-        pair32<D, PMASK, KERN>(qw, h, kf, ua, K.pl32, P);
-      }
+    typedef const __attribute__((address_space(4))) int cint_t;   // uniform loads via the scalar cache
+    cint_t* srec = (cint_t*)F.H.rec32;
+    auto lds = [&](int64_t k) {
+      int4 h;
+      h.x = srec[4 * k];
+      h.y = D > 1 ? srec[4 * k + 1] : 0;
+      h.z = D > 2 ? srec[4 * k + 2] : 0;
+      h.w = srec[4 * k + 3];
+      return h;
     };
-    if (full) run(std::false_type{});
-    else run(std::true_type{});
-    if (comp) {
-      kahan_fold<N>(Sm, Cc, P);
-#pragma unroll
-      for (int r = 0; r < N; ++r) { out[r].x = Sm[r]; out[r].y = -Cc[r]; }
-    } else {
-#pragma unroll
-      for (int r = 0; r < N; ++r) { out[r].x = P[r]; out[r].y = 0.0; }
-    }
+    if (full) partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, k0, nrun, nrun, lds, ph, pl);
+    else partial_f32<D, PMASK, KERN, true>(qw, kf, ua, K.pl32, comp, k0, nrun, nmine, lds, ph, pl);
   }
   if (wanted) {
-    double2* dst = F.partials + (w * F.nbw + c) * N;
+    const int64_t at = (w * F.pmax + c) * N;
 #pragma unroll
-    for (int r = 0; r < N; ++r) dst[r] = out[r];
+    for (int r = 0; r < N; ++r) {
+      if constexpr (FP64) F.part64[at + r] = pv[r];
+      else F.part32[at + r] = make_float2(ph[r], pl[r]);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Finish stage (one block per walker): merge the chunk partials (thread t
-// takes a fixed contiguous range of chunks in order, then a fixed block
-// tree), transform, outputs, deposit, chain rule.
+// Split shape, finish launch (one block per walker): thread t merges chunk
+// sums t, t + 128, ... in order, then the block tree; transform, outputs,
+// deposit, chain rule.
 // ---------------------------------------------------------------------------
 template <int D, bool FP64>
-__global__ __launch_bounds__(kBlock) void k_finish_stage(const FArgs F) {
+__global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
   if (F.state[w].bad) return;
-  int64_t nvis = A.n_visible ? A.n_visible[w] : A.n_visible_default;
-  if (nvis < 0 || nvis > F.committed) nvis = F.committed;
-  const int64_t nch = (nvis + kHillsPerBlock - 1) / kHillsPerBlock;
-  const int64_t per = (nch + kBlock - 1) / kBlock;
-  const int64_t c0 = tid * per, c1 = c0 + per < nch ? c0 + per : nch;
-  __shared__ double red[(kBlock / 64) * 2 * N];
+  const int64_t nch = force_chunks(walker_nvis(F, w));
+  __shared__ double red[(kFBlock / 64) * 2 * N];
   __shared__ CvState S;
-  const double2* part = F.partials + w * F.nbw * N;
   float hi[N], lo[N];
   double v64[N];
   const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
 #pragma unroll
   for (int r = 0; r < N; ++r) { hi[r] = 0.0f; lo[r] = 0.0f; v64[r] = 0.0; }
-  for (int64_t q = c0; q < c1; ++q) {
+  for (int64_t c = tid; c < nch; c += kFBlock) {
+    const int64_t at = (w * F.pmax + c) * N;
+    float ph[N], pl[N];
+    double pv[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-      const double2 p = part[q * N + r];
       if (FP64) {
-        v64[r] += p.x;
+        pv[r] = F.part64[at + r];
+        ph[r] = 0.0f;
+        pl[r] = 0.0f;
       } else {
-        const float h2[1] = {(float)p.x}, l2[1] = {(float)p.y};
-        float h1[1] = {hi[r]}, l1[1] = {lo[r]};
-        merge_f32<1>(h1, l1, h2, l2, comp);
-        hi[r] = h1[0];
-        lo[r] = l1[0];
+        const float2 q = F.part32[at + r];
+        ph[r] = q.x;
+        pl[r] = q.y;
+        pv[r] = 0.0;
       }
     }
+    merge_part<N, FP64>(hi, lo, v64, ph, pl, pv, comp);
   }
-  if (FP64) block_sum<N>(v64, red);
+  if (FP64) block_sum<N, kFBlock>(v64, red);
   else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
-  finish_walker<D, FP64>(F, w, hi, lo, v64, S);
+  {
+    const int* src = reinterpret_cast<const int*>(F.state + w);
+    int* dst = reinterpret_cast<int*>(&S);
+    for (int i = tid; i < kStateWords; i += kFBlock) dst[i] = src[i];
+  }
+  Entry ent[kCache];
+  const Entry* in = F.entries + w * (int64_t)kMaxCached;
+  const int total = F.state[w].total;
+#pragma unroll
+  for (int k = 0; k < kCache; ++k) {
+    ent[k].gi = -1;
+    ent[k].li = 0;
+    ent[k].e = 0;
+    ent[k].m = 0.0f;
+    if (k * kFBlock + tid < total) ent[k] = in[k * kFBlock + tid];
+  }
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
 }
 
-template <int D, int STAGE>
-hipError_t go_cv(const FArgs& F, hipStream_t stream) {
-  hipLaunchKernelGGL((k_cv_stage<D, STAGE>), dim3((unsigned)F.A.nw), dim3(kBlock), 0, stream, F);
-  return hipGetLastError();
-}
-
+// ---------------------------------------------------------------------------
+// Launch selection.
+// ---------------------------------------------------------------------------
 template <int D, int PMASK, int KERN, bool FP64>
-hipError_t go_sum(const FArgs& F, hipStream_t stream) {
-  if (F.nbw <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((F.A.nw + 63) / 64), (unsigned)F.nbw);
-  hipLaunchKernelGGL((k_sum_tiles<D, PMASK, KERN, FP64>), grid, dim3(64), 0, stream, F);
+hipError_t go_direct(const FArgs& F, bool fused, hipStream_t stream) {
+  const dim3 walkers((unsigned)F.A.nw);
+  if (fused) {
+    hipLaunchKernelGGL((k_force_fused<D, PMASK, KERN, FP64>), walkers, dim3(kFBlock), 0, stream, F);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_cv_stage<D, kStageSum>), walkers, dim3(kFBlock), 0, stream, F);
+  if (F.pmax > 0) {
+    const dim3 grid((unsigned)F.pmax, (unsigned)((F.A.nw + 63) / 64));
+    hipLaunchKernelGGL((k_sum_parts<D, PMASK, KERN, FP64>), grid, dim3(64), 0, stream, F);
+  }
+  hipLaunchKernelGGL((k_finish_stage<D, FP64>), walkers, dim3(kFBlock), 0, stream, F);
   return hipGetLastError();
 }
 
 template <int D, int KERN>
-hipError_t sum_by_mask(int mask, const FArgs& F, hipStream_t stream) {
+hipError_t direct_by_mask(int mask, const FArgs& F, bool fused, hipStream_t stream) {
   switch (mask) {
-    case 0: return go_sum<D, 0, KERN, false>(F, stream);
-    case 1: return go_sum<D, 1, KERN, false>(F, stream);
-    case 2: if constexpr (D >= 2) return go_sum<D, 2, KERN, false>(F, stream); break;
-    case 3: if constexpr (D >= 2) return go_sum<D, 3, KERN, false>(F, stream); break;
-    case 4: if constexpr (D >= 3) return go_sum<D, 4, KERN, false>(F, stream); break;
-    case 5: if constexpr (D >= 3) return go_sum<D, 5, KERN, false>(F, stream); break;
-    case 6: if constexpr (D >= 3) return go_sum<D, 6, KERN, false>(F, stream); break;
-    case 7: if constexpr (D >= 3) return go_sum<D, 7, KERN, false>(F, stream); break;
+    case 0: return go_direct<D, 0, KERN, false>(F, fused, stream);
+    case 1: return go_direct<D, 1, KERN, false>(F, fused, stream);
+    case 2: if constexpr (D >= 2) return go_direct<D, 2, KERN, false>(F, fused, stream); break;
+    case 3: if constexpr (D >= 2) return go_direct<D, 3, KERN, false>(F, fused, stream); break;
+    case 4: if constexpr (D >= 3) return go_direct<D, 4, KERN, false>(F, fused, stream); break;
+    case 5: if constexpr (D >= 3) return go_direct<D, 5, KERN, false>(F, fused, stream); break;
+    case 6: if constexpr (D >= 3) return go_direct<D, 6, KERN, false>(F, fused, stream); break;
+    case 7: if constexpr (D >= 3) return go_direct<D, 7, KERN, false>(F, fused, stream); break;
     default: break;
   }
   return hipErrorInvalidValue;
 }
 
 template <int D>
-hipError_t launch_d(int mask, const FArgs& F, hipStream_t stream) {
-  if (F.A.cv_only) return go_cv<D, kStageCV>(F, stream);
-  if (F.A.use_grid) return go_cv<D, kStageGrid>(F, stream);
-  hipError_t e = go_cv<D, kStageSum>(F, stream);
-  if (e != hipSuccess) return e;
+hipError_t launch_d(int mask, const FArgs& F, bool fused, hipStream_t stream) {
+  const dim3 walkers((unsigned)F.A.nw);
+  if (F.A.cv_only) {
+    hipLaunchKernelGGL((k_cv_stage<D, kStageCV>), walkers, dim3(kFBlock), 0, stream, F);
+    return hipGetLastError();
+  }
+  if (F.A.use_grid) {
+    hipLaunchKernelGGL((k_cv_stage<D, kStageGrid>), walkers, dim3(kFBlock), 0, stream, F);
+    return hipGetLastError();
+  }
   const bool gauss = F.K.kernel == ABP_K_GAUSS;
-  const bool fp64 = F.A.prec == ABP_PREC_FP64;
-  if (fp64)
-    e = gauss ? go_sum<D, 0, ABP_K_GAUSS, true>(F, stream) : go_sum<D, 0, ABP_K_COMPACT, true>(F, stream);
-  else
-    e = gauss ? sum_by_mask<D, ABP_K_GAUSS>(mask, F, stream) : sum_by_mask<D, ABP_K_COMPACT>(mask, F, stream);
-  if (e != hipSuccess) return e;
-  if (fp64) hipLaunchKernelGGL((k_finish_stage<D, true>), dim3((unsigned)F.A.nw), dim3(kBlock), 0, stream, F);
-  else hipLaunchKernelGGL((k_finish_stage<D, false>), dim3((unsigned)F.A.nw), dim3(kBlock), 0, stream, F);
-  return hipGetLastError();
+  if (F.A.prec == ABP_PREC_FP64)
+    return gauss ? go_direct<D, 0, ABP_K_GAUSS, true>(F, fused, stream)
+                 : go_direct<D, 0, ABP_K_COMPACT, true>(F, fused, stream);
+  return gauss ? direct_by_mask<D, ABP_K_GAUSS>(mask, F, fused, stream)
+               : direct_by_mask<D, ABP_K_COMPACT>(mask, F, fused, stream);
 }
 
 }  // namespace
 
 int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only) {
   if (use_grid || cv_only) return 1;
-  return (int)((committed + kHillsPerBlock - 1) / kHillsPerBlock);
+  return (int)force_chunks(committed);
+}
+
+bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only) {
+  if (use_grid || cv_only) return false;
+  (void)nw;
+  // ABP_FORCE_SHAPE=fused|split overrides the choice (for tests and tuning).
+  if (const char* env = std::getenv("ABP_FORCE_SHAPE")) {
+    if (std::strcmp(env, "fused") == 0) return false;
+    if (std::strcmp(env, "split") == 0) return true;
+  }
+  return committed > kFusedMaxHills;
 }
 
 size_t force_workspace_bytes(int64_t nw, int nbw, int ndim) {
   if (nw <= 0) return 0;
   const size_t st = (size_t)nw * sizeof(CvState);
   const size_t en = (size_t)nw * kMaxCached * sizeof(Entry);
-  const size_t pa = (size_t)nw * (size_t)nbw * (size_t)(ndim + 1) * sizeof(double2);
+  const size_t pa = (size_t)nw * (size_t)nbw * (size_t)(ndim + 1) * 8;   // float2 or double
   return (st + 255) / 256 * 256 + (en + 255) / 256 * 256 + pa;
 }
 
@@ -835,25 +989,28 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
   F.H = H;
   F.A = A;
   F.committed = A.n_visible_default;
-  F.nbw = force_blocks_per_walker(F.committed, A.use_grid, A.cv_only);
+  F.pmax = force_blocks_per_walker(F.committed, A.use_grid, A.cv_only);
   F.state = nullptr;
   F.entries = nullptr;
-  F.partials = nullptr;
-  if (!A.cv_only && !A.use_grid) {
+  F.part32 = nullptr;
+  F.part64 = nullptr;
+  const bool split = force_uses_workspace(A.nw, F.committed, A.use_grid, A.cv_only);
+  if (split) {
     if (!workspace) return hipErrorInvalidValue;
     char* p = static_cast<char*>(workspace);
     const size_t st = ((size_t)A.nw * sizeof(CvState) + 255) / 256 * 256;
     const size_t en = ((size_t)A.nw * kMaxCached * sizeof(Entry) + 255) / 256 * 256;
     F.state = reinterpret_cast<CvState*>(p);
     F.entries = reinterpret_cast<Entry*>(p + st);
-    F.partials = reinterpret_cast<double2*>(p + st + en);
+    F.part32 = reinterpret_cast<float2*>(p + st + en);
+    F.part64 = reinterpret_cast<double*>(p + st + en);
   }
   int mask = 0;
   for (int i = 0; i < K.ndim; ++i) mask |= (K.periodic[i] ? 1 : 0) << i;
   switch (K.ndim) {
-    case 1: return launch_d<1>(mask, F, stream);
-    case 2: return launch_d<2>(mask, F, stream);
-    case 3: return launch_d<3>(mask, F, stream);
+    case 1: return launch_d<1>(mask, F, !split, stream);
+    case 2: return launch_d<2>(mask, F, !split, stream);
+    case 3: return launch_d<3>(mask, F, !split, stream);
     default: return hipErrorInvalidValue;
   }
 }

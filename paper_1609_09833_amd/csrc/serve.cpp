@@ -343,6 +343,11 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     }
     sl.reqs.reserve(B);
     sl.dep_slots.reserve(B);
+    // Workspace for a full batch at the history's capacity (split shape), so
+    // the loop never reallocates; it still grows on demand if this fails.
+    const size_t full = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
+    if (full <= ((size_t)1 << 30) && hipMalloc(&sl.d_ws, full) == hipSuccess) sl.ws_bytes = full;
+    else sl.d_ws = nullptr;
   }
   *out = S;
   return ABP_OK;
@@ -587,10 +592,11 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
       sl.dep_slots.push_back(slot);
     }
     sl.nb = nb;
-    // Workspace for this batch's chunk partials; grows with the history
+    // Workspace for this batch's partial sums (split shape); grows with the history
     // (the slot is idle here, so freeing its old buffer is safe).
-    const size_t need = abp::force_workspace_bytes(
-        nb, abp::force_blocks_per_walker(sl.version, 0, 0), ncv);
+    const size_t need = abp::force_uses_workspace(nb, sl.version, 0, 0)
+                            ? abp::force_workspace_bytes(nb, abp::force_blocks_per_walker(sl.version, 0, 0), ncv)
+                            : 0;
     if (need > sl.ws_bytes) {
       if (sl.d_ws) SRV_TRY(hipFree(sl.d_ws));
       sl.d_ws = nullptr;

@@ -30,6 +30,8 @@ __device__ __forceinline__ float unit_hash(uint32_t w, uint32_t step, uint32_t a
   return (float)(int32_t)((h >> 16) & 0xffffu) * (1.0f / 32768.0f) - 1.0f;
 }
 
+constexpr int kInFlight = 16;   // mapped-memory loads each thread keeps in flight
+
 __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
@@ -37,26 +39,62 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
   const int32_t n = E.n_atoms[j];
   const int64_t hbase = E.host_base[j];
   if (E.fresh[j]) {
-    for (int i = tid; i < n; i += kBlock) {
-      E.mass[base + i] = E.h_mass[hbase + i];
-      E.fx[base + i] = 0.0f;
-      E.fy[base + i] = 0.0f;
-      E.fz[base + i] = 0.0f;
+    // PCIe reads are issued kInFlight at a time before any is used.
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)kBlock * kInFlight) {
+      float m[kInFlight];
+#pragma unroll
+      for (int u = 0; u < kInFlight; ++u) {
+        const int64_t i = i0 + (int64_t)u * kBlock + tid;
+        m[u] = i < n ? E.h_mass[hbase + i] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kInFlight; ++u) {
+        const int64_t i = i0 + (int64_t)u * kBlock + tid;
+        if (i < n) {
+          E.mass[base + i] = m[u];
+          E.fx[base + i] = 0.0f;
+          E.fy[base + i] = 0.0f;
+          E.fz[base + i] = 0.0f;
+        }
+      }
     }
   }
   const uint32_t w = (uint32_t)E.walker[j];
   const uint32_t st = (uint32_t)E.step[j];
-  for (int q = 0; q < E.nlists; ++q) {
-    const int b = E.list_beg[(int64_t)q * E.nb + j];
-    const int len = E.list_len[(int64_t)q * E.nb + j];
-    for (int e = tid; e < len; e += kBlock) {
-      const int32_t i = E.list_idx[b + e];
-      if (i < 0 || i >= n) continue;                 // the bias kernels flag it
-      const int64_t g = base + i;
-      const int64_t hg = hbase + i;
-      E.x[g] = __fadd_rn(E.h_x0[hg], __fmul_rn(E.amplitude, unit_hash(w, st, (uint32_t)i, 0u)));
-      E.y[g] = __fadd_rn(E.h_y0[hg], __fmul_rn(E.amplitude, unit_hash(w, st, (uint32_t)i, 1u)));
-      E.z[g] = __fadd_rn(E.h_z0[hg], __fmul_rn(E.amplitude, unit_hash(w, st, (uint32_t)i, 2u)));
+  // CV atoms of all lists, flattened: entry r of list q sits at r - start[q].
+  int start[7];
+  start[0] = 0;
+  for (int q = 0; q < E.nlists; ++q) start[q + 1] = start[q] + E.list_len[(int64_t)q * E.nb + j];
+  const int total = start[E.nlists];
+  for (int r0 = 0; r0 < total; r0 += kBlock * kInFlight) {
+    int32_t atom[kInFlight];
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int r = r0 + u * kBlock + tid;
+      atom[u] = -1;
+      if (r < total) {
+        int q = 0;
+        while (q + 1 < E.nlists && r >= start[q + 1]) ++q;
+        const int32_t i = E.list_idx[E.list_beg[(int64_t)q * E.nb + j] + (r - start[q])];
+        atom[u] = (i >= 0 && i < n) ? i : -1;        // the bias kernels flag a bad index
+      }
+    }
+    float px[kInFlight], py[kInFlight], pz[kInFlight];
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int64_t hg = hbase + (atom[u] < 0 ? 0 : atom[u]);   // atom 0 stands in: always valid
+      px[u] = E.h_x0[hg];
+      py[u] = E.h_y0[hg];
+      pz[u] = E.h_z0[hg];
+    }
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      if (atom[u] < 0) continue;
+      const int64_t g = base + atom[u];
+      const uint32_t a = (uint32_t)atom[u];
+      E.x[g] = __fadd_rn(px[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 0u)));
+      E.y[g] = __fadd_rn(py[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 1u)));
+      E.z[g] = __fadd_rn(pz[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 2u)));
       E.fx[g] = 0.0f;
       E.fy[g] = 0.0f;
       E.fz[g] = 0.0f;

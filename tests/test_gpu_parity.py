@@ -365,6 +365,91 @@ def test_c3_alone_equals_in_the_mix(c3):
         assert np.array_equal(host(d1.fz), full[4][b:b + n])
 
 
+# ---------------------------------------------------------------------------
+# launch shapes: many walkers take the fused launch, few walkers with a long
+# history the split launches; both compute the same decomposition of the sum,
+# so they agree bitwise, also with a different n_visible per walker
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def shape_walkers():
+    device()
+    return W.ligand_pocket_walkers(seed=21, n_walkers=256, atoms_lo=1000, atoms_hi=2000)
+
+
+SHAPE_CASES = [(W.KERNEL_GAUSS, W.TRANSFORM_PLAIN, KAHAN), (W.KERNEL_GAUSS, W.TRANSFORM_PLAIN, NAIVE),
+               (W.KERNEL_GAUSS, W.TRANSFORM_PLAIN, FP64), (W.KERNEL_COMPACT, W.TRANSFORM_MABP, KAHAN),
+               (W.KERNEL_COMPACT, W.TRANSFORM_MABP, FP64)]
+
+
+@pytest.mark.parametrize("kernel,transform,prec", SHAPE_CASES)
+def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, monkeypatch):
+    import dataclasses
+    wk = shape_walkers
+    spec, hills = W.ligand_pocket_hills(seed=22, n_hills=40000)
+    if kernel == W.KERNEL_COMPACT:
+        spec = dataclasses.replace(spec, kernel=kernel, width=(0.3, 0.9), p=2)
+    spec = dataclasses.replace(spec, transform=transform)
+    ctx = make_ctx(spec, hills)
+    rng = np.random.default_rng(23)
+    nvis = rng.integers(0, hills.n + 1, wk.nw)
+    nvis[:6] = [0, 1, 63, 64, 65, hills.n]                # chunk boundaries of the decomposition
+    # fused: 256 walkers in one launch
+    monkeypatch.setenv("ABP_FORCE_SHAPE", "fused")
+    dw = abp.DeviceWalkers(wk)
+    s, V, dV = abp.bias_force(ctx, dw, prec=prec, n_visible=nvis)
+    abp.abp_sync(ctx)
+    s, V, dV = host(s), host(V), host(dV)
+    F = [host(dw.fx).copy(), host(dw.fy).copy(), host(dw.fz).copy()]
+    # the oracle with the same per-walker prefixes
+    z = np.zeros(wk.total_atoms)
+    ref = oracle.bias_force(spec, hills.centers, hills.heights, wk, z, z, z, n_visible=nvis)
+    assert np.all(ref[6] == 0)
+    sA0 = np.zeros(wk.nw)
+    sA = np.zeros((wk.ncv, wk.nw))
+    for w in range(wk.nw):
+        n = int(nvis[w])
+        _, _, a0, a = oracle.bias_eval(spec, hills.centers[:, :n], hills.heights[:n], ref[0][:, w:w + 1])
+        sA0[w], sA[:, w] = a0[0], a[:, 0]
+    tol = tol_for(prec)
+    floor = floor_for(prec, hills)
+    check_bound("shape V", V, ref[1], sA0, tol, floor)
+    check_bound("shape dVds", dV, ref[2], sA, tol, floor * 1e4 * max(1.0, 1.0 / min(spec.width[:2]) ** 2))
+    assert V[0] == 0.0 and np.all(dV[:, 0] == 0.0)        # no visible hills
+    # split: a 64-walker batch (mixed partial counts in a wave) and single walkers
+    monkeypatch.setenv("ABP_FORCE_SHAPE", "split")
+    d64 = abp.DeviceWalkers(_first_walkers(wk, 64))
+    s64, V64, dV64 = abp.bias_force(ctx, d64, prec=prec, n_visible=nvis[:64])
+    assert np.array_equal(host(s64), s[:, :64])
+    assert np.array_equal(host(V64), V[:64])
+    assert np.array_equal(host(dV64), dV[:, :64])
+    n64 = int(wk.atom_base[63] + wk.n_atoms[63])
+    assert np.array_equal(host(d64.fx), F[0][:n64])
+    for w in (0, 5, 77, 255):
+        d1 = abp.DeviceWalkers(W.single_walker(wk, w))
+        s1, V1, dV1 = abp.bias_force(ctx, d1, prec=prec, n_visible=nvis[w:w + 1])
+        assert np.array_equal(host(s1)[:, 0], s[:, w])
+        assert np.array_equal(host(V1)[0], V[w])
+        assert np.array_equal(host(dV1)[:, 0], dV[:, w])
+        b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+        assert np.array_equal(host(d1.fy), F[1][b:b + n])
+    monkeypatch.delenv("ABP_FORCE_SHAPE")
+    d2 = abp.DeviceWalkers(W.single_walker(wk, 3))           # the default shape for this history
+    s2, V2, _ = abp.bias_force(ctx, d2, prec=prec, n_visible=nvis[3:4])
+    assert np.array_equal(host(V2)[0], V[3])
+    abp.abp_sync(ctx)
+
+
+def _first_walkers(wk, k):
+    """The first k walkers of a batch as a batch of their own (pools and lists truncated)."""
+    end = int(wk.atom_base[k - 1] + wk.n_atoms[k - 1])
+    off = wk.list_off[:, :, :k + 1].copy()
+    idx_end = int(off.max())
+    return W.Walkers(n_atoms=wk.n_atoms[:k].copy(), atom_base=wk.atom_base[:k].copy(), x=wk.x[:end].copy(),
+                     y=wk.y[:end].copy(), z=wk.z[:end].copy(), mass=wk.mass[:end].copy(), kinds=wk.kinds,
+                     list_off=off, list_idx=wk.list_idx.copy(), ref_x=wk.ref_x.copy(), ref_y=wk.ref_y.copy(),
+                     ref_z=wk.ref_z.copy())
+
+
 def test_rmsd_cv_paper_benchmark_shape():
     """Two 4-atom offset-RMSD CVs on a 99,137-atom walker (mABP, compact hills)."""
     device()
