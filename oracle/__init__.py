@@ -38,7 +38,7 @@ class _Bias(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("kernel", C.c_int32), ("width", C.c_double * 3), ("p", C.c_int32),
                 ("transform", C.c_int32), ("kT", C.c_double), ("b", C.c_double),
-                ("c", C.c_double), ("grid_n", C.c_int32 * 3)]
+                ("c", C.c_double), ("grid_n", C.c_int32 * 3), ("quantize", C.c_int32)]
 
 
 _lib = None
@@ -65,6 +65,10 @@ def lib():
         L.orc_transform.argtypes = [P, i64, P, P, P, P, P]
         L.orc_grid_coord.restype = C.c_double
         L.orc_grid_coord.argtypes = [P, C.c_int32, i64]
+        L.orc_snap_index.restype = i64
+        L.orc_snap_index.argtypes = [P, C.c_int32, C.c_double]
+        L.orc_snap.restype = C.c_double
+        L.orc_snap.argtypes = [P, C.c_int32, C.c_double]
         L.orc_grid_nodes.restype = C.c_int32
         L.orc_grid_nodes.argtypes = [P, i64, P, P, i64, P, P]
         L.orc_grid_eval.restype = C.c_int32
@@ -104,6 +108,7 @@ def bias_struct(spec) -> _Bias:
     b.p = int(spec.p)
     b.transform = int(spec.transform)
     b.kT, b.b, b.c = float(spec.kT), float(spec.b), float(spec.c)
+    b.quantize = int(getattr(spec, "quantize", 0))
     return b
 
 
@@ -160,6 +165,16 @@ def bias_eval(spec, centers, heights, q):
 def grid_coord(spec, axis, j):
     b = bias_struct(spec)
     return lib().orc_grid_coord(C.byref(b), int(axis), int(j))
+
+
+def snap_index(spec, axis, x):
+    """Nearest grid node index of x on an axis (the quantised mode)."""
+    return int(lib().orc_snap_index(C.byref(bias_struct(spec)), int(axis), float(x)))
+
+
+def snap(spec, axis, x):
+    """Coordinate of the nearest grid node of x on an axis."""
+    return lib().orc_snap(C.byref(bias_struct(spec)), int(axis), float(x))
 
 
 def grid_size(spec):

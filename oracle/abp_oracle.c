@@ -87,6 +87,32 @@ static int bias_ok(const orc_bias* B) {
   return 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Quantised mode: the trajectory's CV value is approximated by the nearest  */
+/* grid point before the update (text before eq. update). Rounding: floor of  */
+/* (x - lo)/dx + 1/2, so a point halfway between nodes goes to the upper one. */
+/* ------------------------------------------------------------------------ */
+static double node_spacing(const orc_bias* B, int i) {
+  const double L = B->hi[i] - B->lo[i];
+  return B->periodic[i] ? L / (double)B->grid_n[i] : L / (double)(B->grid_n[i] - 1);
+}
+
+int64_t orc_snap_index(const orc_bias* B, int32_t axis, double x) {
+  const double n = (double)B->grid_n[axis];
+  double t = floor((x - B->lo[axis]) / node_spacing(B, axis) + 0.5);
+  if (!isfinite(t)) t = 0.0;
+  if (B->periodic[axis]) t -= n * floor(t / n);
+  if (t < 0.0) t = 0.0;
+  if (t > n - 1.0) t = n - 1.0;
+  return (int64_t)t;
+}
+
+double orc_snap(const orc_bias* B, int32_t axis, double x) {
+  const double j = (double)orc_snap_index(B, axis, x);
+  const double p = j * node_spacing(B, axis);
+  return B->lo[axis] + p;
+}
+
 /* Displacement s - c on axis i, minimum image on periodic axes. */
 static double axis_delta(const orc_bias* B, int i, double s, double c) {
   double d = s - c;
@@ -103,10 +129,14 @@ static void hill_sum_one(const orc_bias* B, int64_t nh, const double* centers,
                          double* h, double* dh, double* A0, double* A) {
   const int d = B->ndim;
   nsum H = {0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}}, AH = {0, 0}, AG[3] = {{0, 0}, {0, 0}, {0, 0}};
+  double x[3];
+  for (int i = 0; i < d; ++i) x[i] = B->quantize ? orc_snap(B, i, s[i]) : s[i];
   for (int64_t k = 0; k < nh; ++k) {
     double val[3], der[3];
     for (int i = 0; i < d; ++i) {
-      double delta = axis_delta(B, i, s[i], centers[(int64_t)i * nh + k]);
+      double ck = centers[(int64_t)i * nh + k];
+      if (B->quantize) ck = orc_snap(B, i, ck);
+      double delta = axis_delta(B, i, x[i], ck);
       orc_kernel_1d(B->kernel, B->width[i], B->p, delta, &val[i], &der[i]);
     }
     double w = heights[k];
@@ -226,7 +256,9 @@ int32_t orc_grid_nodes(const orc_bias* B, int64_t nh, const double* centers, con
     for (int64_t k = 0; k < nh; ++k) {
       double val[3], der[3];
       for (int i = 0; i < d; ++i) {
-        double delta = axis_delta(B, i, x[i], centers[(int64_t)i * nh + k]);
+        double c = centers[(int64_t)i * nh + k];
+        if (B->quantize) c = orc_snap(B, i, c);
+        double delta = axis_delta(B, i, x[i], c);
         orc_kernel_1d(B->kernel, B->width[i], B->p, delta, &val[i], &der[i]);
       }
       for (int m = 0; m < nm; ++m) {
@@ -261,6 +293,21 @@ int32_t orc_grid_eval(const orc_bias* B, const double* H, int64_t nq, const doub
   const int nm = 1 << d;
   int64_t clamped = 0;
   for (int64_t jq = 0; jq < nq; ++jq) {
+    if (B->quantize) {
+      /* nearest-node look-up: h and h'_i of eq. btraj-grad at xi* */
+      int64_t node = 0, stride = 1;
+      int was_out = 0;
+      for (int i = 0; i < d; ++i) {
+        double s = q[(int64_t)i * nq + jq];
+        if (!B->periodic[i] && !(s >= B->lo[i] && s <= B->hi[i])) was_out = 1;
+        node += orc_snap_index(B, i, s) * stride;
+        stride *= (int64_t)B->grid_n[i];
+      }
+      clamped += was_out;
+      h[jq] = H[node * nm];
+      for (int k = 0; k < d; ++k) dh[(int64_t)k * nq + jq] = H[node * nm + (1 << k)];
+      continue;
+    }
     int64_t j0[3], j1[3];
     double dx[3], phi[3][2][2], dphi[3][2][2];
     int was_clamped = 0;

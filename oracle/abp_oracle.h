@@ -36,6 +36,9 @@ typedef struct {
   int32_t transform;     /* ORC_PLAIN or ORC_MABP */
   double kT, b, c;       /* mABP parameters (eq. apfm) */
   int32_t grid_n[3];     /* grid nodes per axis */
+  int32_t quantize;      /* 1: hills and evaluation points are moved to their nearest grid
+                            node (the nearest-grid-point approximation that precedes
+                            eq. update), and the grid is read at that node */
 } orc_bias;
 
 /* Minimum-image displacement on a periodic axis. */
@@ -55,6 +58,12 @@ int32_t orc_hill_sum(const orc_bias* B, int64_t nh, const double* centers, const
 int32_t orc_transform(const orc_bias* B, int64_t nq, const double* h, const double* dh,
                       double* V, double* dV, double* slope);
 
+/* Nearest grid node of x on an axis: index floor((x - lo)/dx + 1/2), taken
+ * mod n on a periodic axis and clamped to [0, n-1] otherwise (dx the node
+ * spacing); orc_snap returns that node's coordinate lo + j dx. */
+int64_t orc_snap_index(const orc_bias* B, int32_t axis, double x);
+double orc_snap(const orc_bias* B, int32_t axis, double x);
+
 /* Grid node coordinate j on axis i. */
 double orc_grid_coord(const orc_bias* B, int32_t axis, int64_t j);
 
@@ -66,7 +75,9 @@ int32_t orc_grid_nodes(const orc_bias* B, int64_t nh, const double* centers, con
 
 /* Tensor-product cubic Hermite interpolation of h and its analytic gradient
  * from node arrays H[nodes][2^ndim]. Out-of-range queries on non-periodic axes
- * are clamped to the grid; their number is returned in *n_clamped. */
+ * are clamped to the grid; their number is returned in *n_clamped. In the
+ * quantised mode h and dh are the value and first-derivative arrays at the
+ * query's nearest node instead. */
 int32_t orc_grid_eval(const orc_bias* B, const double* H, int64_t nq, const double* q,
                       double* h, double* dh, int64_t* n_clamped);
 

@@ -53,6 +53,7 @@ class BiasSpec:
     c: float = 0.001
     grid_n: tuple = (0, 0, 0)
     capacity: int = 0
+    quantize: int = 0
 
     def padded(self):
         """Return the 3-wide tuples the C structures use."""

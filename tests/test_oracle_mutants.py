@@ -22,8 +22,13 @@ MUTANTS = {
     "compact_deriv_factor": ("*deriv = -2.0 * p * delta", "*deriv = -1.0 * p * delta"),
     "wrap_floor": ("return delta - period * nearbyint(delta / period);", "return delta - period * floor(delta / period);"),
     "grad_product_index": ("if (j != i) g *= val[j];", "if (j == i) g *= val[j];"),
-    "centers_transposed": ("double delta = axis_delta(B, i, s[i], centers[(int64_t)i * nh + k]);",
-                           "double delta = axis_delta(B, i, s[i], centers[(int64_t)k * d + i]);"),
+    "centers_transposed": ("double ck = centers[(int64_t)i * nh + k];",
+                           "double ck = centers[(int64_t)k * d + i];"),
+    "snap_truncates": ("double t = floor((x - B->lo[axis]) / node_spacing(B, axis) + 0.5);",
+                       "double t = floor((x - B->lo[axis]) / node_spacing(B, axis));"),
+    "quantised_hills_not_snapped": ("if (B->quantize) ck = orc_snap(B, i, ck);", "(void)0;"),
+    "quantised_stride": ("stride *= (int64_t)B->grid_n[i];", "stride *= (int64_t)B->grid_n[0];"),
+    "quantised_query_not_snapped": ("x[i] = B->quantize ? orc_snap(B, i, s[i]) : s[i];", "x[i] = s[i];"),
     "mabp_grad_drop_b": ("dV[i] = c * b * kT * dh[i] / den;", "dV[i] = c * kT * dh[i] / den;"),
     "mabp_value_factor": ("log1p(c * (1.0 - b) * h)", "log1p(c * b * h)"),
     "hermite_basis_term": ("phi[0][1] = t3 - 2 * t2 + t;", "phi[0][1] = t3 - 2 * t2;"),

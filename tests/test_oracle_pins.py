@@ -552,3 +552,93 @@ def test_bias_force_flags_bad_walkers():
     out = oracle.bias_force(spec, cen, hts, bad, z, z, z)
     assert list(out[6]) == [oracle.ORC_E_NONFINITE, 0]
     assert np.isnan(out[1][0]) and np.isfinite(out[1][1])
+
+
+# --------------------------------------------------------------------------
+# Quantised mode: the CV value is replaced by its nearest grid node before
+# the update (text before eq. update); the force is a look-up at that node
+# (eq. btraj-grad at xi*). The paper's discretisation: 480 x 480 nodes over
+# [0, 12] nm, compact hills with a = 10 node spacings.
+# --------------------------------------------------------------------------
+PAPER_DX = 12.0 / 479
+
+
+def paper_grid_spec(**kw):
+    base = dict(ndim=2, periodic=(0, 0), lo=(0.0, 0.0), hi=(12.0, 12.0), kernel=W.KERNEL_COMPACT,
+                width=(10 * PAPER_DX, 10 * PAPER_DX), p=20, grid_n=(480, 480), quantize=1)
+    base.update(kw)
+    return W.BiasSpec(**base)
+
+
+def test_snap_is_the_nearest_node():
+    spec = paper_grid_spec()
+    rng = np.random.default_rng(31)
+    xs = rng.uniform(0.0, 12.0, 2000)
+    nodes = np.arange(480) * PAPER_DX
+    for x in xs:
+        j = oracle.snap_index(spec, 0, x)
+        best = np.abs(nodes - x).min()
+        assert abs(nodes[j] - x) <= best + 1e-12            # brute force over every node
+        assert oracle.snap(spec, 0, x) == pytest.approx(nodes[j], abs=1e-12)
+    # outside the range: the edge nodes
+    assert oracle.snap_index(spec, 0, -3.0) == 0 and oracle.snap_index(spec, 0, 40.0) == 479
+    # exactly halfway goes to the upper node (node spacing 1 makes the midpoint exact)
+    half = W.BiasSpec(ndim=1, periodic=(0,), lo=(0.0,), hi=(10.0,), grid_n=(11,), quantize=1)
+    assert oracle.snap_index(half, 0, 2.5) == 3 and oracle.snap_index(half, 0, 2.4999999) == 2
+    # periodic axis: nearest node under the wrap
+    per = W.BiasSpec(ndim=1, periodic=(1,), lo=(-PI,), hi=(PI,), grid_n=(256,), quantize=1)
+    d = 2 * PI / 256
+    assert oracle.snap_index(per, 0, PI - 0.1 * d) == 0
+    assert oracle.snap_index(per, 0, -PI - 0.6 * d) == 255
+    assert oracle.snap_index(per, 0, -PI + 3.4 * d) == 3
+
+
+def test_quantised_look_up_3d():
+    """The look-up indexes a 3-D grid with mixed periodicity correctly."""
+    spec = W.BiasSpec(ndim=3, periodic=(0, 1, 1), lo=(0.0, -PI, -PI), hi=(1.2, PI, PI), width=(0.25, 0.9, 1.1),
+                      kernel=W.KERNEL_COMPACT, p=2, grid_n=(13, 10, 8), quantize=1)
+    rng = np.random.default_rng(33)
+    cen = np.vstack([rng.uniform(0.1, 1.1, 25), rng.uniform(-PI, PI, (2, 25))])
+    w = rng.uniform(0.5, 1.5, 25)
+    q = np.vstack([rng.uniform(0.0, 1.2, 200), rng.uniform(-PI, PI, (2, 200))])
+    H = oracle.grid_all(spec, cen, w)
+    hg, dhg, _ = oracle.grid_eval(spec, H, q)
+    hs, dhs, A0, A = oracle.hill_sum(spec, cen, w, q)
+    np.testing.assert_allclose(hg, hs, rtol=1e-12, atol=1e-14 * A0.max())
+    np.testing.assert_allclose(dhg, dhs, rtol=1e-12, atol=1e-14 * A.max())
+
+
+def test_quantised_look_up_equals_sum_at_the_node():
+    """Grid arrays at xi* equal the direct sum of the node-centred hills at xi*,
+    and the sum at a point equals a brute-force sum built from the 1-D kernel."""
+    spec = paper_grid_spec(grid_n=(60, 50), width=(10 * 12.0 / 59, 10 * 12.0 / 49), p=4)
+    rng = np.random.default_rng(32)
+    cen = rng.uniform(3.0, 9.0, (2, 40))
+    w = rng.uniform(0.5, 1.5, 40)
+    q = rng.uniform(2.0, 10.0, (2, 300))
+    H = oracle.grid_all(spec, cen, w)
+    hg, dhg, _ = oracle.grid_eval(spec, H, q)
+    hs, dhs, A0, A = oracle.hill_sum(spec, cen, w, q)
+    np.testing.assert_allclose(hg, hs, rtol=1e-12, atol=1e-14 * A0.max())
+    np.testing.assert_allclose(dhg, dhs, rtol=1e-12, atol=1e-14 * A.max())
+    dxs = (12.0 / 59, 12.0 / 49)
+    node = lambda x, i: np.floor(x / dxs[i] + 0.5) * dxs[i]
+    for j in range(0, 300, 37):
+        v = 0.0
+        for k in range(40):
+            f0 = oracle.kernel_1d(spec.kernel, spec.width[0], spec.p, node(q[0, j], 0) - node(cen[0, k], 0))[0]
+            f1 = oracle.kernel_1d(spec.kernel, spec.width[1], spec.p, node(q[1, j], 1) - node(cen[1, k], 1))[0]
+            v += w[k] * f0 * f1
+        assert hs[j] == pytest.approx(v, rel=1e-12, abs=1e-14)
+
+
+def test_quantised_hill_stencil_is_nbase_squared():
+    """A deposit off the nodes is moved to its node, so it touches 19 x 19
+    nodes with a = 10 spacings (eq. Cupdate runs only over those)."""
+    spec = paper_grid_spec()
+    ids = np.arange(480 * 480)
+    for c in ([[5.0], [6.0]], [[5.0 + 0.37 * PAPER_DX], [6.0 - 0.21 * PAPER_DX]]):
+        H = oracle.grid_nodes(spec, c, [1.0], ids)
+        assert int(np.count_nonzero(H[:, 0])) == 19 * 19
+        j0, j1 = oracle.snap_index(spec, 0, c[0][0]), oracle.snap_index(spec, 1, c[1][0])
+        assert H[j0 + 480 * j1, 0] == 1.0                   # S(0) = 1 at the hill's own node
