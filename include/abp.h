@@ -104,6 +104,15 @@ typedef struct {
   int32_t grid_n[3];     /* grid nodes per axis (>= 2 each), or all 0 for no grid.
                             Periodic axis: nodes lo + j (hi-lo)/n, j < n.
                             Non-periodic: nodes lo + j (hi-lo)/(n-1), j < n. */
+  int32_t quantize;      /* 0, or 1 for the paper's quantised mode (needs a grid): the
+                            CV value is replaced by its nearest grid node xi* (section
+                            "Streamlined bias potential updates", before eq. update),
+                            node index floor((s - lo)/dx + 1/2), taken mod n on a
+                            periodic axis and clamped to [0, n-1] otherwise, with
+                            dx the node spacing. Deposited hills are centred on
+                            xi*; GRID evaluation looks up the value and first-
+                            derivative arrays at the query's xi* (no interpolation)
+                            and DIRECT evaluation sums the hills at xi*. */
   int64_t capacity;      /* maximum number of hills the history holds, >= 1 */
 } abp_bias_desc;
 

@@ -29,6 +29,26 @@ __device__ __forceinline__ double work64(const Consts& K, int axis, double s) {
   return K.periodic[axis] ? (s - K.lo[axis]) * K.inv_period[axis] : s;
 }
 
+// Nearest grid node of x on one axis (the quantised mode): node index
+// floor((x - lo)/dx + 1/2), mod n on a periodic axis, clamped to [0, n-1]
+// otherwise; snap_coord returns the node's coordinate lo + j dx.
+__device__ __forceinline__ double snap_index(const Consts& K, int axis, double x) {
+  const double n = (double)K.grid_n[axis];
+  double t = floor((x - K.lo[axis]) / K.grid_dx[axis] + 0.5);
+  if (!isfinite(t)) t = 0.0;
+  if (K.periodic[axis]) t -= n * floor(t / n);
+  return fmin(fmax(t, 0.0), n - 1.0);   // (the periodic remainder is already in range)
+}
+
+__device__ __forceinline__ double snap_coord(const Consts& K, int axis, double x) {
+  return __dadd_rn(K.lo[axis], __dmul_rn(snap_index(K, axis, x), K.grid_dx[axis]));
+}
+
+// The coordinate a sum or deposit uses: x itself, or its node when quantised.
+__device__ __forceinline__ double eval_coord(const Consts& K, int axis, double x) {
+  return K.quant ? snap_coord(K, axis, x) : x;
+}
+
 __device__ __forceinline__ uint32_t rec_word(const int4& h, int i) {
   return (uint32_t)(i == 0 ? h.x : (i == 1 ? h.y : h.z));
 }
@@ -173,9 +193,24 @@ __device__ __forceinline__ void hermite_eval(const Consts& K, const double* __re
                                              const double (&s)[D], double& h, double (&dh)[D],
                                              bool& clamped) {
   constexpr int NM = 1 << D;
+  clamped = false;
+  if (K.quant) {
+    // nearest-node look-up of h and the first derivatives (no interpolation)
+    int64_t node = 0, stride = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      if (!K.periodic[i] && !(s[i] >= K.lo[i] && s[i] <= K.hi[i])) clamped = true;
+      node += (int64_t)snap_index(K, i, s[i]) * stride;
+      stride *= K.grid_n[i];
+    }
+    const double* src = grid + node * NM;
+    h = src[0];
+#pragma unroll
+    for (int k = 0; k < D; ++k) dh[k] = src[1 << k];
+    return;
+  }
   int64_t j0[D], j1[D];
   double A[D][2][2], B[D][2][2];   // basis for [cell end][datum: value/derivative]
-  clamped = false;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const int64_t n = K.grid_n[i];

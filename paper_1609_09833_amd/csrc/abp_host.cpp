@@ -106,6 +106,8 @@ abp_status check_desc(const abp_bias_desc* d) {
     if (any_grid && (d->grid_n[i] < 2 || d->grid_n[i] > (1 << 20)))
       return fail(ABP_E_INVAL, "grid_n[%d] must be 2..2^20 when a grid is requested", i);
   }
+  if (d->quantize != 0 && d->quantize != 1) return fail(ABP_E_INVAL, "quantize must be 0 or 1");
+  if (d->quantize && !any_grid) return fail(ABP_E_INVAL, "the quantised mode needs a grid (grid_n)");
   if (d->capacity < 1 || d->capacity > ((int64_t)1 << 34)) return fail(ABP_E_INVAL, "capacity out of range");
   return ABP_OK;
 }
@@ -116,6 +118,7 @@ void make_consts(const abp_bias_desc& d, Consts& K) {
   K.kernel = d.kernel;
   K.p = d.kernel == ABP_K_COMPACT ? d.p : 1;
   K.transform = d.transform;
+  K.quant = d.quantize;
   K.kT = d.kT;
   K.b = d.b;
   K.c = d.c;

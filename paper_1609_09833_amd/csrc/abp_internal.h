@@ -35,6 +35,7 @@ enum : int32_t { kErrIndex = 1 << 0, kErrNonfinite = 1 << 1, kErrInval = 1 << 2 
 // period (turns) wrapped with rint; non-periodic ones are raw.
 struct Consts {
   int32_t ndim, kernel, p, transform;
+  int32_t quant;                   // 1: evaluate and deposit at the nearest grid node
   int32_t periodic[3];
   double lo[3], hi[3], period[3], inv_period[3];
   // FP32 path, per axis: Gaussian exponent factor on the working displacement

@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(const DirectArgs A) {
   const int64_t iq = iq0 < A.nq ? iq0 : A.nq - 1;
   double tq[D], P[D + 1];
 #pragma unroll
-  for (int i = 0; i < D; ++i) tq[i] = work64(A.K, i, load_q(A, i, iq));
+  for (int i = 0; i < D; ++i) tq[i] = work64(A.K, i, eval_coord(A.K, i, load_q(A, i, iq)));
 #pragma unroll
   for (int r = 0; r <= D; ++r) P[r] = 0.0;
   for (int64_t t0 = 0; t0 < A.nvis; t0 += kTile64) {

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_f32(const DirectArgs A) {
     int64_t iq = first + j;
     iq = iq < A.nq ? iq : A.nq - 1;
 #pragma unroll
-    for (int i = 0; i < D; ++i) qw[j][i] = work32(A.K, i, load_q(A, i, iq));
+    for (int i = 0; i < D; ++i) qw[j][i] = work32(A.K, i, eval_coord(A.K, i, load_q(A, i, iq)));
 #pragma unroll
     for (int r = 0; r <= D; ++r) { S[j][r] = 0.0f; Cc[j][r] = 0.0f; P[j][r] = 0.0f; }
   }

@@ -196,8 +196,9 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
   if (!isfinite(hw) || hw < 0.0) { atomicOr(A.err, kErrNonfinite); hw = 0.0; }
   uint32_t words[3] = {0u, 0u, 0u};
   for (int a = 0; a < D; ++a) {
-    F.H.c64[a * F.H.capacity + slot] = S.s[a];
-    words[a] = work32(F.K, a, S.s[a]);
+    const double c = eval_coord(F.K, a, S.s[a]);   // quantised mode: the nearest node
+    F.H.c64[a * F.H.capacity + slot] = c;
+    words[a] = work32(F.K, a, c);
   }
   F.H.w64[slot] = hw;
   int4 rec;
@@ -741,7 +742,7 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
   if constexpr (FP64) {
     double tq[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) tq[i] = work64(K, i, S.s[i]);
+    for (int i = 0; i < D; ++i) tq[i] = work64(K, i, eval_coord(K, i, S.s[i]));
     for (int64_t c = tid; c < nch; c += kFBlock) {
       const int n = chunk_terms(nvis, c);
       double pv[N];
@@ -755,7 +756,7 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
     float kf[D], ua[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      qw[i] = work32(K, i, S.s[i]);
+      qw[i] = work32(K, i, eval_coord(K, i, S.s[i]));
       kf[i] = K.kf32[i];
       ua[i] = K.ua32[i];
     }
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
   const int64_t k0 = c * kChunkHills;
   double s[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) s[a] = F.state[wc].s[a];
+  for (int a = 0; a < D; ++a) s[a] = eval_coord(K, a, F.state[wc].s[a]);
   float ph[N], pl[N];
   double pv[N];
   if constexpr (FP64) {

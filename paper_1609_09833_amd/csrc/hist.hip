@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_append(const AppendArgs A) {
     for (int i = 0; i < A.K.ndim; ++i) c[i] = A.K.lo[i];
     w = 0.0;
   }
+  for (int i = 0; i < A.K.ndim; ++i) c[i] = eval_coord(A.K, i, c[i]);   // quantised mode: the node
   int4 rec;
   uint32_t words[3] = {0u, 0u, 0u};
   for (int i = 0; i < A.K.ndim; ++i) {

@@ -429,3 +429,28 @@ def engine_positions(x0, y0, z0, walker, step, atoms, amplitude):
         p[atoms] = p[atoms] + (amp * u).astype(np.float32)
         out.append(p)
     return out
+
+
+def paper_grid_2d(seed=0, n_hills=20000, a_spacings=10, p=20, step=0.02, start=(1.0, 1.0)):
+    """The paper's discretisation for its ligand-binding runs, in the quantised
+    mode: two CVs on [0, 12] nm with 480 x 480 grid nodes, compact hills S_a^p
+    with a = a_spacings node spacings (10 or 20 in the paper) and p = 20, mABP
+    with c = 0.001, b = 0.9 at 300 K. Hill centres follow a Gaussian random walk
+    from `start` with step sd `step` nm, reflected into [0, 12] (a stand-in for
+    the visited CV values); heights 1 (one count per deposit).
+    Draw order: the walk's steps.
+    """
+    dx = 12.0 / 479
+    spec = BiasSpec(ndim=2, periodic=(0, 0), lo=(0.0, 0.0), hi=(12.0, 12.0), kernel=KERNEL_COMPACT,
+                    width=(a_spacings * dx, a_spacings * dx), p=p, transform=TRANSFORM_MABP, kT=KT_300K,
+                    b=0.9, c=0.001, grid_n=(480, 480), quantize=1)
+    rng = np.random.default_rng(seed + 5)
+    steps = rng.normal(0.0, step, (2, n_hills))
+    c = np.empty((2, n_hills))
+    x = np.array(start, dtype=np.float64)
+    for k in range(n_hills):
+        x = x + steps[:, k]
+        x = np.where(x < 0.0, -x, x)
+        x = np.where(x > 12.0, 24.0 - x, x)
+        c[:, k] = x
+    return spec, Hills(c, np.ones(n_hills))

@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_1609_09833_amd import workloads as W
 from tests.gpu_common import device, to_dev, host, sample_idx, cv_atom_grad_abs, torch
-from tests.tolerance import check_bound, rel_err, fp32_floor
+from tests.tolerance import check_bound, rel_err, fp32_floor, fp32_kernel_condition
 
 pytestmark = pytest.mark.gpu
 
@@ -477,6 +477,94 @@ def test_rmsd_cv_paper_benchmark_shape():
         check_bound("rmsd dVds", host(dV), ref[2], sG)
         gabs = cv_atom_grad_abs(wk, ref[0])
         check_forces(wk, dw, ref, sG, gabs)
+
+
+# ---------------------------------------------------------------------------
+# the paper's quantised grid mode: hills moved to their nearest node, compact
+# stencils on a 480 x 480 grid over [0, 12] nm, force by look-up at the node
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def quant():
+    device()
+    spec, hills = W.paper_grid_2d(seed=3, n_hills=6000, start=(0.4, 0.4))
+    ctx = make_ctx(spec, hills, capacity=hills.n + 64)
+    return spec, hills, ctx
+
+
+def test_quantised_deposits_land_on_nodes(quant):
+    spec, hills, ctx = quant
+    cen, hts = abp.abp_hills_export(ctx)
+    snapped = np.array([[oracle.snap(spec, i, x) for x in hills.centers[i]] for i in range(2)])
+    assert np.array_equal(cen, snapped)
+    H = abp.abp_grid_export(ctx)
+    rng = np.random.default_rng(41)
+    live = np.flatnonzero(H[:, 0])
+    ids = np.unique(np.concatenate([rng.choice(live, 1500, replace=False), rng.integers(0, 480 * 480, 500)]))
+    Ho = oracle.grid_nodes(spec, hills.centers, hills.heights, ids)
+    np.testing.assert_allclose(H[ids], Ho, rtol=1e-9, atol=1e-12 * np.abs(Ho).max())
+    # only the nodes within a of some hill's node are touched (eq. Cupdate)
+    assert live.size < 480 * 480 // 4
+
+
+@pytest.mark.parametrize("mode,prec", [(abp.ABP_EVAL_GRID, FP64), (abp.ABP_EVAL_DIRECT, KAHAN),
+                                       (abp.ABP_EVAL_DIRECT, FP64)])
+def test_quantised_eval_matches_oracle(quant, mode, prec):
+    spec, hills, ctx = quant
+    rng = np.random.default_rng(42)
+    dx = 12.0 / 479
+    q = rng.uniform(0.0, 2.0, (2, 3000))
+    q[:, :200] = (rng.integers(0, 80, (2, 200)) + 0.5) * dx       # midpoints between nodes
+    q[:, 200:210] = [[-0.3] * 10, [13.0] * 10]                      # outside: edge nodes
+    V, dV = abp.bias_eval(ctx, to_dev(q), mode=mode, prec=prec)
+    c0, h0 = abp.abp_hills_export(ctx)
+    Vo, dVo, sV, sG = oracle.bias_eval(spec, c0, h0, q)
+    tol = 1e-9 if mode == abp.ABP_EVAL_GRID else tol_for(prec)
+    floor = floor_for(prec, hills) if mode == abp.ABP_EVAL_DIRECT else 0.0
+    gfloor = floor * 1e4 * max(1.0, 1.0 / min(spec.width) ** 2)
+    if mode == abp.ABP_EVAL_DIRECT and prec != FP64:
+        sV, sG = fp32_scales(spec, c0, h0, q, sV, sG)
+    check_bound("quantised V", host(V), Vo, sV, tol, floor)
+    check_bound("quantised dV/ds", host(dV), dVo, sG, tol, gfloor)
+
+
+def fp32_scales(spec, cen, hts, q, sV, sG):
+    """Tolerance scales plus the FP32 compact-kernel conditioning, in units of
+    the 1e-5 bound (2^-21 relative per unit of condition)."""
+    C0, C = fp32_kernel_condition(spec, cen, hts, q, snap=lambda i, x: oracle.snap(spec, i, x)
+                                  if getattr(spec, "quantize", 0) else x)
+    _, _, slope = oracle.transform(spec, *oracle.hill_sum(spec, cen, hts, q)[:2])
+    k = 2.0 ** -21 / 1e-5
+    return sV + k * slope * C0, sG + k * slope[None, :] * C
+
+
+@pytest.mark.parametrize("mode", [abp.ABP_EVAL_DIRECT, abp.ABP_EVAL_GRID])
+def test_quantised_bias_force_and_deposit(quant, mode):
+    """The paper's shape: two 4-atom RMSD CVs on a 99,137-atom walker, forces
+    from the look-up at xi*, and a deposit at xi*."""
+    spec, hills, ctx = quant
+    wk = W.rmsd_walkers(seed=4, n_walkers=2)
+    dw = abp.DeviceWalkers(wk)
+    z = np.zeros(wk.total_atoms)
+    H = abp.abp_grid_export(ctx) if mode == abp.ABP_EVAL_GRID else None
+    c0, h0 = abp.abp_hills_export(ctx)          # node-centred already; snapping again keeps them
+    ref = oracle.bias_force(spec, c0, h0, wk, z, z, z, use_grid=mode == abp.ABP_EVAL_GRID, H=H)
+    assert np.all(ref[6] == 0)
+    slot = abp.abp_reserve(ctx, 1)
+    s, V, dV = abp.bias_force(ctx, dw, mode=mode, deposit_slot=[slot, -1], deposit_height=[1.0, 0.0])
+    abp.abp_commit(ctx, slot + 1)
+    abp.abp_sync(ctx)
+    assert np.abs(host(s) - ref[0]).max() < 1e-12
+    _, _, sV, sG = oracle.bias_eval(spec, c0, h0, ref[0])
+    floor = 0.0 if H is not None else floor_for(KAHAN, hills)
+    gfloor = floor * 1e4 * max(1.0, 1.0 / min(spec.width) ** 2)
+    if H is None:
+        sV, sG = fp32_scales(spec, c0, h0, ref[0], sV, sG)
+    check_bound("quantised force V", host(V), ref[1], sV, 1e-9 if H is not None else 1e-5, floor)
+    check_bound("quantised force dV", host(dV), ref[2], sG, 1e-9 if H is not None else 1e-5, gfloor)
+    check_forces(wk, dw, ref, sG, cv_atom_grad_abs(wk, ref[0]))
+    cen, hts = abp.abp_hills_export(ctx)
+    assert [cen[0, slot], cen[1, slot]] == [oracle.snap(spec, 0, host(s)[0, 0]), oracle.snap(spec, 1, host(s)[1, 0])]
+    assert hts[slot] == 1.0
 
 
 # ---------------------------------------------------------------------------
