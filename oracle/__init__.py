@@ -167,6 +167,19 @@ def grid_coord(spec, axis, j):
     return lib().orc_grid_coord(C.byref(b), int(axis), int(j))
 
 
+def wt_heights(spec, centers, heights, new_centers, w0, dT):
+    """Well-tempered metadynamics heights for hills deposited at new_centers:
+    w = w0 exp(-V(c)/dT), V the bias of the existing hills at c (the hill-height
+    factor by which WTmetaD scales the update, named after eq. Cupdate; the
+    standard form of Barducci, Bussi and Parrinello, 2008)."""
+    new_centers = _f64(new_centers).reshape(spec.ndim, -1)
+    if np.asarray(heights).size == 0:
+        V = np.zeros(new_centers.shape[1])
+    else:
+        V = bias_eval(spec, centers, heights, new_centers)[0]
+    return np.asarray(w0, dtype=np.float64) * np.exp(-V / float(dT))
+
+
 def snap_index(spec, axis, x):
     """Nearest grid node index of x on an axis (the quantised mode)."""
     return int(lib().orc_snap_index(C.byref(bias_struct(spec)), int(axis), float(x)))

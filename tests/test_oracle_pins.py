@@ -642,3 +642,35 @@ def test_quantised_hill_stencil_is_nbase_squared():
         assert int(np.count_nonzero(H[:, 0])) == 19 * 19
         j0, j1 = oracle.snap_index(spec, 0, c[0][0]), oracle.snap_index(spec, 1, c[1][0])
         assert H[j0 + 480 * j1, 0] == 1.0                   # S(0) = 1 at the hill's own node
+
+
+# --------------------------------------------------------------------------
+# Well-tempered heights w0 exp(-V/dT) (WTmetaD's hill-height factor)
+# --------------------------------------------------------------------------
+def test_wt_height_closed_forms():
+    spec = W.BiasSpec(ndim=2, periodic=(1, 1), lo=(-PI, -PI), hi=(PI, PI), width=(0.3, 0.3))
+    c = np.array([[0.4], [-1.0]])
+    # empty history: the full height
+    assert oracle.wt_heights(spec, np.zeros((2, 0)), np.zeros(0), c, 0.7, 2.5)[0] == 0.7
+    # one hill of height w at the same point: V = w
+    assert oracle.wt_heights(spec, c, [1.3], c, 0.7, 2.5)[0] == pytest.approx(0.7 * math.exp(-1.3 / 2.5), rel=1e-14)
+    # one sigma away on one axis: V = w e^(-1/2)
+    c1 = np.array([[0.4 + 0.3], [-1.0]])
+    assert oracle.wt_heights(spec, c, [1.3], c1, 0.7, 2.5)[0] == pytest.approx(
+        0.7 * math.exp(-1.3 * math.exp(-0.5) / 2.5), rel=1e-13)
+
+
+def test_wt_repeated_deposits_follow_the_log_law():
+    """Deposits at one point, one per step: V_{n+1} = V_n + w0 exp(-V_n/dT),
+    whose continuous limit is V(n) = dT ln(1 + n w0 / dT); dT -> infinity gives
+    plain metadynamics, V = n w0."""
+    spec = W.BiasSpec(ndim=1, periodic=(1,), lo=(-PI,), hi=(PI,), width=(0.35,))
+    c = np.array([[0.25]])
+    for dT, n, rel in ((2.5, 400, 2e-2), (1e12, 50, 1e-9)):
+        cen, hts = np.zeros((1, 0)), np.zeros(0)
+        for _ in range(n):
+            w = oracle.wt_heights(spec, cen, hts, c, 0.05, dT)[0]
+            cen, hts = np.hstack([cen, c]), np.append(hts, w)
+        V = hts.sum()
+        expect = dT * math.log1p(n * 0.05 / dT) if dT < 1e6 else n * 0.05
+        assert V == pytest.approx(expect, rel=rel)
