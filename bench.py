@@ -178,6 +178,64 @@ def latency_leg(abp, W, torch, calls=200):
     return out
 
 
+def quantised_leg(abp, W, torch, n_hills=20000, single=2000, steps=10):
+    """The paper's own discretisation in the quantised mode: 480 x 480 nodes over
+    [0, 12] nm, compact hills (a = 10 node spacings, p = 20), mABP; hills are
+    moved to their nearest node and the force is a look-up at the node. Times
+    a batched deposit, one-hill deposits (one per MD step, as in the paper),
+    the look-up for 1,048,576 queries and one walker's bias_force."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    spec, hills = W.paper_grid_2d(seed=7, n_hills=n_hills + single)
+    out = {"grid": "480 x 480 over [0, 12] nm", "a_spacings": 10, "p": 20,
+           "node_updates_per_deposit": 19 * 19}
+    ctx = abp.Context(spec, capacity=n_hills + single)
+    cen = torch.as_tensor(hills.centers, device=dev)
+    hts = torch.as_tensor(hills.heights, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    abp.bias_deposit(ctx, cen[:, :n_hills].contiguous(), hts[:n_hills].contiguous())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out["batched_deposit"] = {"hills": n_hills, "ms": ms, "hills_per_s": n_hills / ms * 1e3}
+    one = [(cen[:, k:k + 1].contiguous(), hts[k:k + 1].contiguous()) for k in range(n_hills, n_hills + single)]
+    it = iter(one)
+
+    def dep():
+        c, h = next(it)
+        abp.bias_deposit(ctx, c, h)
+    el, _ = timed(dep, single - 10, 10, stream)
+    out["one_hill_deposit_us"] = el / (single - 10) * 1e6
+    q = torch.as_tensor(np.random.default_rng(8).uniform(0.0, 4.0, (2, 1 << 20)).astype(np.float32), device=dev)
+    V = torch.empty(1 << 20, dtype=torch.float32, device=dev)
+    dV = torch.empty((2, 1 << 20), dtype=torch.float32, device=dev)
+
+    def look():
+        abp.bias_eval(ctx, q, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
+    el, _ = timed(look, steps, 2, stream)
+    out["look_up"] = {"queries": 1 << 20, "walker_steps_per_s": (1 << 20) * steps / el,
+                      "ms_per_step": el / steps * 1e3}
+    wk = W.rmsd_walkers(seed=2, n_walkers=1)
+    dw = abp.DeviceWalkers(wk, device=dev)
+    s_o = torch.empty((2, 1), dtype=torch.float64, device=dev)
+    V_o = torch.empty(1, dtype=torch.float64, device=dev)
+    dV_o = torch.empty((2, 1), dtype=torch.float64, device=dev)
+
+    def force():
+        abp.bias_force(ctx, dw, mode=abp.ABP_EVAL_GRID, s=s_o, V=V_o, dVds=dV_o)
+    el, _ = timed(force, 200, 10, stream)
+    out["one_walker_bias_force_us"] = el / 200 * 1e6
+    abp.abp_sync(ctx)
+    ctx.close()
+    log(f"bench: quantised grid: batched deposit {out['batched_deposit']['hills_per_s']:.3e} hills/s, one-hill "
+        f"deposit {out['one_hill_deposit_us']:.1f} us, look-up {out['look_up']['walker_steps_per_s']:.3e} "
+        f"walker-steps/s, one-walker force {out['one_walker_bias_force_us']:.1f} us")
+    return out
+
+
 def serving_leg(abp, W, torch, window_s=1.0):
     """The serving workload: 4,096 walkers of 1,000-20,000 atoms (COM distance
     + torsion CVs), Poisson arrivals at 200,000 requests/s to uniformly chosen
@@ -262,7 +320,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
-    ap.add_argument("--only", choices=("headline", "force", "serving"), default=None,
+    ap.add_argument("--only", choices=("headline", "force", "serving", "quantised"), default=None,
                     help="run one leg only (profiling): the headline direct sum, the fused bias-force "
                          "workload, or the serving workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -284,6 +342,9 @@ def main():
         args.only = "headline"
     if args.only == "force":
         print(json.dumps({"extra": force_leg(abp, W, torch, args, stream)}), flush=True)
+        return
+    if args.only == "quantised":
+        print(json.dumps({"extra": {"quantised_grid": quantised_leg(abp, W, torch)}}), flush=True)
         return
     if args.only == "serving":
         print(json.dumps({"extra": {"serving": serving_leg(abp, W, torch)}}), flush=True)
@@ -377,6 +438,7 @@ def main():
                           "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
     log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
     extra.update(force_leg(abp, W, torch, args, stream))
+    extra["quantised_grid"] = quantised_leg(abp, W, torch)
     if not args.no_serving:
         sv = serving_leg(abp, W, torch)
         head = sv["hist200k_budget512MiB"]

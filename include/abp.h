@@ -114,6 +114,11 @@ typedef struct {
                             derivative arrays at the query's xi* (no interpolation)
                             and DIRECT evaluation sums the hills at xi*. */
   int64_t capacity;      /* maximum number of hills the history holds, >= 1 */
+  double wt_dT;          /* 0, or k_B dT > 0 (energy units) for well-tempered metadynamics
+                            heights: a deposited hill's height is multiplied by
+                            exp(-V(xi*)/wt_dT), V the bias at its centre before it is
+                            added (the WTmetaD hill-height factor, section "Streamlined
+                            bias potential updates" after eq. Cupdate) */
 } abp_bias_desc;
 
 /* CV definition for a batch of nw walkers (device arrays, caller-owned).
@@ -169,7 +174,10 @@ abp_status abp_destroy(abp_ctx* ctx);
  * that is not gets height 0 and raises ABP_E_NONFINITE at abp_sync. Returns
  * ABP_E_CAPACITY (nothing appended) if the history would overflow. n = 0 is a
  * no-op. The appended hills are visible to work enqueued after this call on
- * the same stream. */
+ * the same stream. With wt_dT > 0 every height is scaled by
+ * exp(-V/wt_dT), V the bias at the hill's centre from the FP64 direct sum over
+ * the hills committed before this call (one deposit per call is the
+ * per-step rule exactly; in a batch the hills do not see each other). */
 abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* centers,
                         const void* heights, abp_stream stream);
 
@@ -202,9 +210,9 @@ abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* wa
  * result is bitwise the same in any batch and either shape.
  * Writes s[ncv][nw], V[nw], dVds[ncv][nw] (FP64).
  * deposit_slot (optional, [nw]): if deposit_slot[w] >= 0, the hill centred at
- * walker w's s with height deposit_height[w] (NULL: 1.0) is written to that
- * history slot, which must have been reserved with abp_reserve and is made
- * visible by abp_commit. Atom lists must follow abp_cv_desc's rules. */
+ * walker w's s with height deposit_height[w] (NULL: 1.0; times exp(-V[w]/wt_dT)
+ * when wt_dT > 0) is written to that history slot, which must have been
+ * reserved with abp_reserve and is made visible by abp_commit. Atom lists must follow abp_cv_desc's rules. */
 abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
                       const abp_walkers* walkers, const int64_t* n_visible,
                       const int64_t* deposit_slot, const double* deposit_height,

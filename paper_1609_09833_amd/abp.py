@@ -42,7 +42,8 @@ class BiasDesc(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("kernel", C.c_int32), ("width", C.c_double * 3), ("p", C.c_int32),
                 ("transform", C.c_int32), ("kT", C.c_double), ("b", C.c_double), ("c", C.c_double),
-                ("grid_n", C.c_int32 * 3), ("quantize", C.c_int32), ("capacity", C.c_int64)]
+                ("grid_n", C.c_int32 * 3), ("quantize", C.c_int32), ("capacity", C.c_int64),
+                ("wt_dT", C.c_double)]
 
 
 class CvDesc(C.Structure):
@@ -155,6 +156,7 @@ def make_desc(spec, capacity):
     d.kT, d.b, d.c = float(spec.kT), float(spec.b), float(spec.c)
     d.quantize = int(getattr(spec, "quantize", 0))
     d.capacity = int(capacity)
+    d.wt_dT = float(getattr(spec, "wt_dT", 0.0))
     return d
 
 

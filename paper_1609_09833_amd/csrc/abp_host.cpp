@@ -31,6 +31,8 @@ struct abp_ctx {
   size_t scratch_bytes = 0;
   void* fws = nullptr;                // bias_force: CV state, atom lists, partial sums
   size_t fws_bytes = 0;
+  void* wt_buf = nullptr;             // bias_deposit: bias at new centres (well-tempered heights)
+  size_t wt_bytes = 0;
 
   HistView hist() const {
     HistView h;
@@ -106,6 +108,7 @@ abp_status check_desc(const abp_bias_desc* d) {
     if (any_grid && (d->grid_n[i] < 2 || d->grid_n[i] > (1 << 20)))
       return fail(ABP_E_INVAL, "grid_n[%d] must be 2..2^20 when a grid is requested", i);
   }
+  if (!(d->wt_dT >= 0.0) || !std::isfinite(d->wt_dT)) return fail(ABP_E_INVAL, "wt_dT must be >= 0");
   if (d->quantize != 0 && d->quantize != 1) return fail(ABP_E_INVAL, "quantize must be 0 or 1");
   if (d->quantize && !any_grid) return fail(ABP_E_INVAL, "the quantised mode needs a grid (grid_n)");
   if (d->capacity < 1 || d->capacity > ((int64_t)1 << 34)) return fail(ABP_E_INVAL, "capacity out of range");
@@ -119,6 +122,7 @@ void make_consts(const abp_bias_desc& d, Consts& K) {
   K.p = d.kernel == ABP_K_COMPACT ? d.p : 1;
   K.transform = d.transform;
   K.quant = d.quantize;
+  K.wt_dT = d.wt_dT;
   K.kT = d.kT;
   K.b = d.b;
   K.c = d.c;
@@ -259,6 +263,7 @@ void free_all(abp_ctx* ctx) {
   if (ctx->clamped) (void)hipFree(ctx->clamped);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->fws) (void)hipFree(ctx->fws);
+  if (ctx->wt_buf) (void)hipFree(ctx->wt_buf);
 }
 
 }  // namespace
@@ -330,8 +335,26 @@ abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* ce
     return fail(ABP_E_CAPACITY, "history capacity %lld exceeded", (long long)ctx->desc.capacity);
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)stream;
+  const void* vbias = nullptr;
+  if (ctx->desc.wt_dT > 0.0 && ctx->committed > 0) {
+    // well-tempered heights: the bias at each new centre, FP64 direct sum over
+    // the hills committed so far (V and dV/ds in the centres' dtype)
+    const size_t esz = dtype == ABP_F64 ? sizeof(double) : sizeof(float);
+    const size_t need = (size_t)n * (1 + ctx->desc.ndim) * esz;
+    if (need > ctx->wt_bytes) {
+      if (ctx->wt_buf) (void)hipFree(ctx->wt_buf);
+      ctx->wt_buf = nullptr;
+      ctx->wt_bytes = 0;
+      if (hipMalloc(&ctx->wt_buf, need) != hipSuccess) return fail(ABP_E_NOMEM, "cannot allocate %zu bytes", need);
+      ctx->wt_bytes = need;
+    }
+    char* buf = static_cast<char*>(ctx->wt_buf);
+    HIP_TRY(abp::launch_direct_sum(ctx->K, ctx->hist(), ctx->committed, ABP_PREC_FP64, n, dtype == ABP_F64 ? 1 : 0,
+                                   centers, buf, buf + (size_t)n * esz, s));
+    vbias = buf;
+  }
   HIP_TRY(abp::launch_hist_append(ctx->K, ctx->hist(), ctx->committed, n, dtype == ABP_F64 ? 1 : 0,
-                                  centers, heights, ctx->err, s));
+                                  centers, heights, vbias, ctx->err, s));
   const int64_t k0 = ctx->committed;
   ctx->committed += n;
   ctx->reserved = ctx->committed;

@@ -47,6 +47,7 @@ struct Consts {
   double kf64[3], ua64[3], gs64[3], per64[3];
   double pl64;
   double kT, b, c;                 // mABP transform
+  double wt_dT;                    // > 0: well-tempered deposit heights w exp(-V / wt_dT)
   double width[3];                 // sigma_i (Gaussian) or a_i (compact), real units
   // grid
   int32_t grid_n[3];
@@ -65,9 +66,11 @@ struct HistView {
 // and return hipSuccess or the launch error.
 hipError_t launch_hist_init(const HistView& H, int ndim, hipStream_t stream);
 
+// vbias (optional, same dtype as the centres): the bias at each centre; with
+// K.wt_dT > 0 each height is multiplied by exp(-vbias / wt_dT).
 hipError_t launch_hist_append(const Consts& K, const HistView& H, int64_t first, int64_t n,
                               int dtype_f64, const void* centers, const void* heights,
-                              int32_t* err, hipStream_t stream);
+                              const void* vbias, int32_t* err, hipStream_t stream);
 
 hipError_t launch_direct_sum(const Consts& K, const HistView& H, int64_t n_visible, abp_prec prec,
                              int64_t nq, int q_f64, const void* q, void* V, void* dVds,

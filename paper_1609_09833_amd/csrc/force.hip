@@ -193,6 +193,7 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
     atomicOr(A.err, kErrInval);
     return;
   }
+  if (F.K.wt_dT > 0.0) hw *= exp(-V / F.K.wt_dT);    // well-tempered height
   if (!isfinite(hw) || hw < 0.0) { atomicOr(A.err, kErrNonfinite); hw = 0.0; }
   uint32_t words[3] = {0u, 0u, 0u};
   for (int a = 0; a < D; ++a) {

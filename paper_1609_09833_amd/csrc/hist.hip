@@ -16,6 +16,7 @@ struct AppendArgs {
   int32_t f64;
   const void* centers;   // [ndim][n]
   const void* heights;   // [n]
+  const void* vbias;     // [n] or NULL: bias at each centre (well-tempered heights)
   int32_t* err;
 };
 
@@ -32,6 +33,10 @@ __global__ __launch_bounds__(kBlock) void k_hist_append(const AppendArgs A) {
   }
   double w = A.f64 ? static_cast<const double*>(A.heights)[k]
                    : (double)static_cast<const float*>(A.heights)[k];
+  if (A.vbias && A.K.wt_dT > 0.0) {
+    const double v = A.f64 ? static_cast<const double*>(A.vbias)[k] : (double)static_cast<const float*>(A.vbias)[k];
+    w *= exp(-v / A.K.wt_dT);
+  }
   ok = ok && isfinite(w) && w >= 0.0;
   if (!ok) {
     atomicOr(A.err, kErrNonfinite);
@@ -78,7 +83,7 @@ hipError_t launch_hist_init(const HistView& H, int ndim, hipStream_t stream) {
 
 hipError_t launch_hist_append(const Consts& K, const HistView& H, int64_t first, int64_t n,
                               int dtype_f64, const void* centers, const void* heights,
-                              int32_t* err, hipStream_t stream) {
+                              const void* vbias, int32_t* err, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   AppendArgs A;
   A.K = K;
@@ -88,6 +93,7 @@ hipError_t launch_hist_append(const Consts& K, const HistView& H, int64_t first,
   A.f64 = dtype_f64;
   A.centers = centers;
   A.heights = heights;
+  A.vbias = vbias;
   A.err = err;
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_hist_append, dim3((unsigned)blocks), dim3(kBlock), 0, stream, A);

@@ -54,6 +54,7 @@ class BiasSpec:
     grid_n: tuple = (0, 0, 0)
     capacity: int = 0
     quantize: int = 0
+    wt_dT: float = 0.0
 
     def padded(self):
         """Return the 3-wide tuples the C structures use."""

@@ -51,8 +51,9 @@ def test_struct_layout_matches_binding(tmp_path):
 #include <stddef.h>
 #include "abp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\\n", sizeof(abp_bias_desc), offsetof(abp_bias_desc, capacity),
-         offsetof(abp_bias_desc, grid_n), offsetof(abp_bias_desc, kT));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(abp_bias_desc), offsetof(abp_bias_desc, capacity),
+         offsetof(abp_bias_desc, grid_n), offsetof(abp_bias_desc, kT), offsetof(abp_bias_desc, quantize),
+         offsetof(abp_bias_desc, wt_dT));
   printf("%zu %zu %zu\\n", sizeof(abp_cv_desc), offsetof(abp_cv_desc, list_off), offsetof(abp_cv_desc, ref_z));
   printf("%zu %zu %zu\\n", sizeof(abp_walkers), offsetof(abp_walkers, x), offsetof(abp_walkers, fz));
   printf("%zu %zu %zu\\n", sizeof(abp_server_desc), offsetof(abp_server_desc, amplitude),
@@ -68,7 +69,7 @@ int main(void) {
     # the binding's mirrors (the binding imports torch, which is available here)
     from paper_1609_09833_amd import abp
     assert vals[0] == [C.sizeof(abp.BiasDesc), abp.BiasDesc.capacity.offset, abp.BiasDesc.grid_n.offset,
-                       abp.BiasDesc.kT.offset]
+                       abp.BiasDesc.kT.offset, abp.BiasDesc.quantize.offset, abp.BiasDesc.wt_dT.offset]
     assert vals[1] == [C.sizeof(abp.CvDesc), abp.CvDesc.list_off.offset, abp.CvDesc.ref_z.offset]
     assert vals[2] == [C.sizeof(abp.WalkersDesc), abp.WalkersDesc.x.offset, abp.WalkersDesc.fz.offset]
     assert vals[3] == [C.sizeof(abp.ServerDesc), abp.ServerDesc.amplitude.offset, abp.ServerDesc.cv_kind.offset]

@@ -568,6 +568,70 @@ def test_quantised_bias_force_and_deposit(quant, mode):
 
 
 # ---------------------------------------------------------------------------
+# well-tempered metadynamics heights w0 exp(-V/dT) on deposit
+# ---------------------------------------------------------------------------
+def _wt_spec(dT=2.5):
+    import dataclasses
+    spec, hills = W.torsion_2d(seed=5, n_hills=2000, n_queries=8)[:2]
+    return dataclasses.replace(spec, wt_dT=dT, grid_n=(0, 0)), hills
+
+
+def test_wt_batch_deposit_heights():
+    device()
+    spec, hills = _wt_spec()
+    ctx = make_ctx(spec, W.Hills(hills.centers, np.ones(hills.n)), capacity=hills.n + 200)
+    c0, h0 = abp.abp_hills_export(ctx)
+    assert np.all(h0 == 1.0)          # one call into an empty history: no hill sees another
+    rng = np.random.default_rng(51)
+    new = rng.uniform(-PI, PI, (2, 100))
+    abp.bias_deposit(ctx, to_dev(new), to_dev(np.full(100, 0.8)))
+    abp.abp_sync(ctx)
+    c1, h1 = abp.abp_hills_export(ctx)
+    want = oracle.wt_heights(spec, c0, h0, new, 0.8, 2.5)   # the batch sees the history before it
+    np.testing.assert_allclose(h1[hills.n:], want, rtol=1e-12)
+    assert want.min() < 0.8 * 0.5                             # the history is dense enough to matter
+
+
+def test_wt_one_deposit_per_step_matches_recurrence():
+    device()
+    import dataclasses
+    spec = W.BiasSpec(ndim=1, periodic=(1,), lo=(-PI,), hi=(PI,), width=(0.35,), wt_dT=2.5)
+    ctx = abp.Context(spec, capacity=300)
+    c = np.array([[0.25]])
+    cen, hts = np.zeros((1, 0)), np.zeros(0)
+    for step in range(300):
+        abp.bias_deposit(ctx, to_dev(c), to_dev(np.array([0.05])))
+        w = oracle.wt_heights(spec, cen, hts, c, 0.05, 2.5)[0]
+        cen, hts = np.hstack([cen, c]), np.append(hts, w)
+    abp.abp_sync(ctx)
+    _, h = abp.abp_hills_export(ctx)
+    np.testing.assert_allclose(h, hts, rtol=1e-11)
+
+
+def test_wt_deposit_from_bias_force(c3):
+    """bias_force deposits at each walker's s with height w0 exp(-V_w/dT), V_w the
+    bias the walker saw in the same call."""
+    import dataclasses
+    wk, spec, hills, _, dw, ref, A0, A, gabs = c3
+    wspec = dataclasses.replace(spec, wt_dT=3.0)
+    ctx = make_ctx(wspec, hills, capacity=hills.n + wk.nw)
+    first = abp.abp_reserve(ctx, wk.nw)
+    slots = first + np.arange(wk.nw)
+    for f in (dw.fx, dw.fy, dw.fz):
+        f.zero_()
+    s, V, dV = abp.bias_force(ctx, dw, deposit_slot=slots, deposit_height=np.full(wk.nw, 0.5))
+    abp.abp_commit(ctx, first + wk.nw)
+    abp.abp_sync(ctx)
+    cen, hts = abp.abp_hills_export(ctx)
+    Vg = host(V)
+    np.testing.assert_allclose(hts[slots], 0.5 * np.exp(-Vg / 3.0), rtol=1e-13)
+    # against the oracle's V (1e-5 relative in V moves the height by V/dT * 1e-5)
+    want = oracle.wt_heights(spec, hills.centers, hills.heights, host(s), 0.5, 3.0)
+    np.testing.assert_allclose(hts[slots], want, rtol=1e-5 * (np.abs(ref[1]) + A0).max() / 3.0 + 1e-12)
+    np.testing.assert_array_equal(cen[:, slots], host(s))
+
+
+# ---------------------------------------------------------------------------
 # deposits from bias_force into reserved slots (the serving path)
 # ---------------------------------------------------------------------------
 def test_deposit_from_bias_force_and_commit(c3):
