@@ -80,7 +80,7 @@ def timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(spec, hills, q, target_s=15.0):
+def cpu_baseline(spec, hills, q, target_s=20.0):
     """The FP64 oracle on an evenly spaced sample of the queries, all host cores."""
     import numpy as np
     import oracle
