@@ -190,13 +190,15 @@ def quantised_leg(abp, W, torch, n_hills=20000, single=2000, steps=10):
     spec, hills = W.paper_grid_2d(seed=7, n_hills=n_hills + single)
     out = {"grid": "480 x 480 over [0, 12] nm", "a_spacings": 10, "p": 20,
            "node_updates_per_deposit": 19 * 19}
-    ctx = abp.Context(spec, capacity=n_hills + single)
+    ctx = abp.Context(spec, capacity=2 * n_hills + single)
     cen = torch.as_tensor(hills.centers, device=dev)
     hts = torch.as_tensor(hills.heights, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    first = (cen[:, :n_hills].contiguous(), hts[:n_hills].contiguous())
+    abp.bias_deposit(ctx, *first)          # untimed: the context's scratch is allocated here
     torch.cuda.synchronize()
     e0.record(stream)
-    abp.bias_deposit(ctx, cen[:, :n_hills].contiguous(), hts[:n_hills].contiguous())
+    abp.bias_deposit(ctx, *first)          # the same batch again, timed
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)

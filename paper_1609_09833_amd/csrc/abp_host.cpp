@@ -148,6 +148,7 @@ void make_consts(const abp_bias_desc& d, Consts& K) {
     K.per64[i] = per ? 1.0 : 0.0;
     const double wdt = d.width[i];
     K.width[i] = wdt;
+    K.inv_width[i] = 1.0 / wdt;
     if (d.kernel == ABP_K_GAUSS) {
       K.kf32[i] = (float)(kLog2e * unit32 * unit32 / (2.0 * wdt * wdt));
       K.gs32[i] = -unit32 / (wdt * wdt);

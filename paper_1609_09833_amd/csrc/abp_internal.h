@@ -49,6 +49,7 @@ struct Consts {
   double kT, b, c;                 // mABP transform
   double wt_dT;                    // > 0: well-tempered deposit heights w exp(-V / wt_dT)
   double width[3];                 // sigma_i (Gaussian) or a_i (compact), real units
+  double inv_width[3];             // 1 / width
   // grid
   int32_t grid_n[3];
   double grid_dx[3];               // node spacing per axis

@@ -5,14 +5,16 @@
 // or eq. Cupdate (compact S_a^p), kept as 2^ndim FP64 arrays per node:
 // value, first derivatives and mixed derivatives (entry m differentiates
 // along each axis whose bit is set in m). Storing the mixed derivatives lets
-// the evaluation use tensor-product cubic Hermite interpolation instead of
-// the paper's nearest-node look-up.
+// the evaluation use tensor-product cubic Hermite interpolation; the
+// quantised mode reads the value and first-derivative arrays at the nearest
+// node instead (the paper's look-up).
 //
 // The hill is a product over axes, so per hill and per node tile the block
 // evaluates 1-D factor vectors once (LDS) and forms the node values as
-// outer products: each node costs 2^ndim FMAs per hill. For compact kernels
-// a hill whose support misses the tile is skipped, which is the Nbase^d
-// saving of eq. Cupdate at tile granularity.
+// outer products: each node costs 2^ndim FMAs per hill. Each thread owns
+// COLS x RY nodes of the tile, so one LDS read of a factor pair feeds several
+// FMAs. For compact kernels a hill whose support misses the tile is skipped,
+// which is the Nbase^d saving of eq. Cupdate at tile granularity.
 //
 // Evaluation: one thread per query, 2^ndim corners x 2^ndim arrays gathered
 // from the node-interleaved layout, FP64 arithmetic.
@@ -21,9 +23,13 @@
 namespace abp {
 namespace {
 
-constexpr int kTX = 64;        // nodes along axis 0 per tile (one per lane)
-constexpr int kRY = 8;         // rows along axis 1 per thread
-constexpr int kTY = 4 * kRY;   // rows along axis 1 per tile (4 waves)
+// Tile shape: 64 * COLS nodes along axis 0 (lane l owns columns l, l + 64,
+// ...), 4 * RY along axis 1 (wave v owns rows v*RY ..), one plane along axis
+// 2. Gaussian hills cover every node, so wide 2-D tiles spread each hill's
+// factor evaluations over more nodes; a compact hill touches few nodes, so
+// its tiles stay narrow (less work on the nodes outside its support).
+template <int D, bool WIDE> struct TileShape { static constexpr int COLS = 1, RY = 8; };
+template <> struct TileShape<2, true> { static constexpr int COLS = 2, RY = 8; };
 constexpr int kKC = 16;        // hills per LDS chunk
 constexpr int kMinBlocks = 1024;
 
@@ -43,17 +49,17 @@ struct DepositArgs {
 __device__ __forceinline__ void factor(const Consts& K, int i, double x, double c, double& v, double& d) {
   double delta = x - c;
   if (K.periodic[i]) delta -= K.period[i] * rint(delta * K.inv_period[i]);
-  const double wdt = K.width[i];
+  const double iw = K.inv_width[i];
   if (K.kernel == ABP_K_GAUSS) {
-    const double r = delta / wdt;
+    const double r = delta * iw;
     v = exp(-0.5 * r * r);
-    d = -(delta / (wdt * wdt)) * v;
+    d = -(r * iw) * v;
   } else {
-    const double u = delta / wdt;
+    const double u = delta * iw;
     if (fabs(u) < 1.0) {
-      const double om = 1.0 - u * u;
-      v = exp(-(double)K.p * u * u / om);
-      d = -2.0 * K.p * delta / (wdt * wdt * om * om) * v;
+      const double ro = 1.0 / (1.0 - u * u);
+      v = exp(-(double)K.p * u * u * ro);
+      d = -2.0 * K.p * u * iw * ro * ro * v;
     } else {
       v = 0.0;
       d = 0.0;
@@ -99,17 +105,19 @@ __global__ __launch_bounds__(kBlock) void k_deposit_1d(const DepositArgs A) {
   }
 }
 
-// 2-D and 3-D grids: tile of kTX x kTY nodes (one z plane for 3-D).
-template <int D>
+// 2-D and 3-D grids: tile of 64*COLS x 4*RY nodes (one z plane for 3-D).
+template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
   constexpr int NM = 1 << D;
   constexpr int NY = 1 << (D - 1);          // combos of the derivative bits of axes 1..D-1
-  __shared__ double Xf[kKC][2][kTX];        // axis-0 value / derivative at the tile's nodes
-  __shared__ double Yf[kKC][kTY][NY];       // w * (axis 1 x axis 2 factors)
+  constexpr int COLS = TileShape<D, WIDE>::COLS, RY = TileShape<D, WIDE>::RY;
+  constexpr int TX = 64 * COLS, TY = 4 * RY;
+  __shared__ double2 Xf[kKC][TX];           // axis-0 (value, derivative) at the tile's columns
+  __shared__ double Yf[kKC][TY][NY];        // w * (axis 1 x axis 2 factors)
   __shared__ int live_x[kKC], live_y[kKC];
 
-  const int64_t tiles_x = (A.K.grid_n[0] + kTX - 1) / kTX;
-  const int64_t tiles_y = (A.K.grid_n[1] + kTY - 1) / kTY;
+  const int64_t tiles_x = (A.K.grid_n[0] + TX - 1) / TX;
+  const int64_t tiles_y = (A.K.grid_n[1] + TY - 1) / TY;
   const int64_t tile = blockIdx.x % A.tiles;
   const int s = (int)(blockIdx.x / A.tiles);
   const int64_t tx = tile % tiles_x;
@@ -118,34 +126,35 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t n0 = A.K.grid_n[0], n1 = A.K.grid_n[1];
-  const int64_t x0 = tx * kTX, y0 = ty * kTY;
+  const int64_t x0 = tx * TX, y0 = ty * TY;
   int64_t kb, ke;
   split_range(A, s, kb, ke);
 
   double zc = 0.0;
   if (D == 3) zc = node_coord(A.K, 2, tz);
-  double acc[kRY][NM];
+  double acc[COLS][RY][NM];
 #pragma unroll
-  for (int r = 0; r < kRY; ++r)
+  for (int c = 0; c < COLS; ++c)
 #pragma unroll
-    for (int m = 0; m < NM; ++m) acc[r][m] = 0.0;
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[c][r][m] = 0.0;
 
   for (int64_t kc = kb; kc < ke; kc += kKC) {
     const int nk = (int)(ke - kc < kKC ? ke - kc : kKC);
     __syncthreads();
     if (threadIdx.x < kKC) { live_x[threadIdx.x] = 0; live_y[threadIdx.x] = 0; }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kKC * kTX; idx += kBlock) {
-      const int k = idx / kTX, l = idx % kTX;
+    for (int idx = threadIdx.x; idx < kKC * TX; idx += kBlock) {
+      const int k = idx / TX, l = idx % TX;
       double v = 0.0, d = 0.0;
       const int64_t xj = x0 + l;
       if (k < nk && xj < n0) factor(A.K, 0, node_coord(A.K, 0, xj), A.c64[kc + k], v, d);
-      Xf[k][0][l] = v;
-      Xf[k][1][l] = d;
+      Xf[k][l] = make_double2(v, d);
       if (v != 0.0 || d != 0.0) live_x[k] = 1;
     }
-    for (int idx = threadIdx.x; idx < kKC * kTY; idx += kBlock) {
-      const int k = idx / kTY, r = idx % kTY;
+    for (int idx = threadIdx.x; idx < kKC * TY; idx += kBlock) {
+      const int k = idx / TY, r = idx % TY;
       double yv = 0.0, yd = 0.0, zv = 1.0, zd = 0.0, w = 0.0;
       const int64_t yj = y0 + r;
       if (k < nk && yj < n1) {
@@ -167,34 +176,47 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
     __syncthreads();
     for (int k = 0; k < nk; ++k) {
       if (!(live_x[k] && live_y[k])) continue;     // uniform across the block
-      const double xv = Xf[k][0][lane], xd = Xf[k][1][lane];
+      double2 xf[COLS];
 #pragma unroll
-      for (int r = 0; r < kRY; ++r) {
-        const double* yw = Yf[k][wave * kRY + r];
+      for (int c = 0; c < COLS; ++c) xf[c] = Xf[k][lane + 64 * c];
 #pragma unroll
-        for (int my = 0; my < NY; ++my) {
-          const double f = yw[my];
-          acc[r][2 * my] = __builtin_fma(xv, f, acc[r][2 * my]);
-          acc[r][2 * my + 1] = __builtin_fma(xd, f, acc[r][2 * my + 1]);
+      for (int r = 0; r < RY; ++r) {
+        double f[NY];
+        const double* yw = Yf[k][wave * RY + r];
+#pragma unroll
+        for (int my = 0; my < NY; my += 2) {
+          const double2 t = *reinterpret_cast<const double2*>(yw + my);
+          f[my] = t.x;
+          f[my + 1] = t.y;
         }
+#pragma unroll
+        for (int c = 0; c < COLS; ++c)
+#pragma unroll
+          for (int my = 0; my < NY; ++my) {
+            acc[c][r][2 * my] = __builtin_fma(xf[c].x, f[my], acc[c][r][2 * my]);
+            acc[c][r][2 * my + 1] = __builtin_fma(xf[c].y, f[my], acc[c][r][2 * my + 1]);
+          }
       }
     }
   }
-  const int64_t xj = x0 + lane;
-  if (xj >= n0) return;
 #pragma unroll
-  for (int r = 0; r < kRY; ++r) {
-    const int64_t yj = y0 + wave * kRY + r;
-    if (yj >= n1) continue;
-    const int64_t node = xj + n0 * (yj + n1 * tz);
-    if (A.nsplit == 1) {
-      double* g = A.grid + node * NM;
+  for (int c = 0; c < COLS; ++c) {
+    const int64_t xj = x0 + lane + 64 * c;
+    if (xj >= n0) continue;
 #pragma unroll
-      for (int m = 0; m < NM; ++m) g[m] += acc[r][m];
-    } else {
-      double* o = A.scratch + ((int64_t)s * A.K.nodes + node) * NM;
+    for (int r = 0; r < RY; ++r) {
+      const int64_t yj = y0 + wave * RY + r;
+      if (yj >= n1) continue;
+      const int64_t node = xj + n0 * (yj + n1 * tz);
+      if (A.nsplit == 1) {
+        double* g = A.grid + node * NM;
 #pragma unroll
-      for (int m = 0; m < NM; ++m) o[m] = acc[r][m];
+        for (int m = 0; m < NM; ++m) g[m] += acc[c][r][m];
+      } else {
+        double* o = A.scratch + ((int64_t)s * A.K.nodes + node) * NM;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) o[m] = acc[c][r][m];
+      }
     }
   }
 }
@@ -220,36 +242,58 @@ struct EvalArgs {
   unsigned long long* n_clamped;
 };
 
+// Queries per thread: independent corner gathers in flight (1-D/2-D); the
+// 3-D interpolation is register-heavy enough on its own.
+template <int D> struct EvalQ { static constexpr int value = D == 3 ? 1 : 4; };
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_grid_eval(const EvalArgs A) {
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= A.nq) return;
-  double s[D];
+  constexpr int kEvalQ = EvalQ<D>::value;
+  const int64_t base = (int64_t)blockIdx.x * kBlock * kEvalQ + threadIdx.x;
+  double h[kEvalQ], dh[kEvalQ][D];
+  bool clamped[kEvalQ];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-    s[i] = A.q_f64 ? static_cast<const double*>(A.q)[i * A.nq + j]
-                   : (double)static_cast<const float*>(A.q)[i * A.nq + j];
-  double h, dh[D], V, dV[D];
-  bool clamped;
-  hermite_eval<D>(A.K, A.grid, s, h, dh, clamped);
-  if (clamped && A.n_clamped) atomicAdd(A.n_clamped, 1ull);
-  apply_transform<D>(A.K, h, dh, V, dV);
-  if (A.q_f64) {
-    static_cast<double*>(A.V)[j] = V;
+  for (int u = 0; u < kEvalQ; ++u) {
+    int64_t j = base + (int64_t)u * kBlock;
+    j = j < A.nq ? j : A.nq - 1;
+    double s[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) static_cast<double*>(A.dV)[i * A.nq + j] = dV[i];
-  } else {
-    static_cast<float*>(A.V)[j] = (float)V;
-#pragma unroll
-    for (int i = 0; i < D; ++i) static_cast<float*>(A.dV)[i * A.nq + j] = (float)dV[i];
+    for (int i = 0; i < D; ++i)
+      s[i] = A.q_f64 ? static_cast<const double*>(A.q)[i * A.nq + j]
+                     : (double)static_cast<const float*>(A.q)[i * A.nq + j];
+    hermite_eval<D>(A.K, A.grid, s, h[u], dh[u], clamped[u]);
   }
+#pragma unroll
+  for (int u = 0; u < kEvalQ; ++u) {
+    const int64_t j = base + (int64_t)u * kBlock;
+    if (j >= A.nq) continue;
+    if (clamped[u] && A.n_clamped) atomicAdd(A.n_clamped, 1ull);
+    double V, dV[D];
+    apply_transform<D>(A.K, h[u], dh[u], V, dV);
+    if (A.q_f64) {
+      static_cast<double*>(A.V)[j] = V;
+#pragma unroll
+      for (int i = 0; i < D; ++i) static_cast<double*>(A.dV)[i * A.nq + j] = dV[i];
+    } else {
+      static_cast<float*>(A.V)[j] = (float)V;
+#pragma unroll
+      for (int i = 0; i < D; ++i) static_cast<float*>(A.dV)[i * A.nq + j] = (float)dV[i];
+    }
+  }
+}
+
+template <int D, bool WIDE>
+int64_t tiles_of(const Consts& K) {
+  constexpr int TX = 64 * TileShape<D, WIDE>::COLS, TY = 4 * TileShape<D, WIDE>::RY;
+  int64_t t = ((K.grid_n[0] + TX - 1) / TX) * ((K.grid_n[1] + TY - 1) / TY);
+  if (D == 3) t *= K.grid_n[2];
+  return t;
 }
 
 int64_t node_tiles(const Consts& K) {
   if (K.ndim == 1) return (K.grid_n[0] + kBlock - 1) / kBlock;
-  int64_t t = ((K.grid_n[0] + kTX - 1) / kTX) * ((K.grid_n[1] + kTY - 1) / kTY);
-  if (K.ndim == 3) t *= K.grid_n[2];
-  return t;
+  if (K.ndim == 3) return tiles_of<3, false>(K);
+  return K.kernel == ABP_K_GAUSS ? tiles_of<2, true>(K) : tiles_of<2, false>(K);
 }
 
 int split_for(const Consts& K, int64_t nhills) {
@@ -288,8 +332,11 @@ hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, i
   const unsigned blocks = (unsigned)(A.tiles * A.nsplit);
   switch (K.ndim) {
     case 1: hipLaunchKernelGGL(k_deposit_1d, dim3(blocks), dim3(kBlock), 0, stream, A); break;
-    case 2: hipLaunchKernelGGL(k_deposit_nd<2>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
-    case 3: hipLaunchKernelGGL(k_deposit_nd<3>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
+    case 2:
+      if (K.kernel == ABP_K_GAUSS) hipLaunchKernelGGL((k_deposit_nd<2, true>), dim3(blocks), dim3(kBlock), 0, stream, A);
+      else hipLaunchKernelGGL((k_deposit_nd<2, false>), dim3(blocks), dim3(kBlock), 0, stream, A);
+      break;
+    case 3: hipLaunchKernelGGL((k_deposit_nd<3, false>), dim3(blocks), dim3(kBlock), 0, stream, A); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -313,11 +360,11 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, int64_t nq, int
   A.dV = dVds;
   A.q_f64 = q_f64;
   A.n_clamped = n_clamped;
-  const unsigned blocks = (unsigned)((nq + kBlock - 1) / kBlock);
+  auto blocks = [nq](int qp) { return (unsigned)((nq + (int64_t)kBlock * qp - 1) / ((int64_t)kBlock * qp)); };
   switch (K.ndim) {
-    case 1: hipLaunchKernelGGL(k_grid_eval<1>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
-    case 2: hipLaunchKernelGGL(k_grid_eval<2>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
-    case 3: hipLaunchKernelGGL(k_grid_eval<3>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
+    case 1: hipLaunchKernelGGL(k_grid_eval<1>, dim3(blocks(EvalQ<1>::value)), dim3(kBlock), 0, stream, A); break;
+    case 2: hipLaunchKernelGGL(k_grid_eval<2>, dim3(blocks(EvalQ<2>::value)), dim3(kBlock), 0, stream, A); break;
+    case 3: hipLaunchKernelGGL(k_grid_eval<3>, dim3(blocks(EvalQ<3>::value)), dim3(kBlock), 0, stream, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
