@@ -129,7 +129,6 @@ def force_leg(abp, W, torch, args, stream):
     log(f"bench: cv_compute {wk.nw * args.steps / el5:.4e} walker-steps/s")
     abp.abp_sync(fctx)
     fctx.close()
-    extra["single_walker_latency"] = latency_leg(abp, W, torch)
     return extra
 
 
@@ -322,7 +321,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
-    ap.add_argument("--only", choices=("headline", "force", "serving", "quantised"), default=None,
+    ap.add_argument("--only", choices=("headline", "force", "latency", "serving", "quantised"), default=None,
                     help="run one leg only (profiling): the headline direct sum, the fused bias-force "
                          "workload, or the serving workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -344,6 +343,9 @@ def main():
         args.only = "headline"
     if args.only == "force":
         print(json.dumps({"extra": force_leg(abp, W, torch, args, stream)}), flush=True)
+        return
+    if args.only == "latency":
+        print(json.dumps({"extra": {"single_walker_latency": latency_leg(abp, W, torch)}}), flush=True)
         return
     if args.only == "quantised":
         print(json.dumps({"extra": {"quantised_grid": quantised_leg(abp, W, torch)}}), flush=True)
@@ -440,6 +442,7 @@ def main():
                           "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
     log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
     extra.update(force_leg(abp, W, torch, args, stream))
+    extra["single_walker_latency"] = latency_leg(abp, W, torch)
     extra["quantised_grid"] = quantised_leg(abp, W, torch)
     if not args.no_serving:
         sv = serving_leg(abp, W, torch)
