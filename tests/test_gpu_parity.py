@@ -298,10 +298,11 @@ def check_forces(wk, dw, ref, A, gabs, tol=1e-5):
         g = gabs[j]                                   # [ncv, 3]
         for a in range(wk.ncv):
             scale[:, k] += (np.abs(dVo[a, w]) + A[a, w]) * g[a]
-    check_bound("forces", F[:, atoms], Fo[:, atoms], scale, tol)
+    ratio = check_bound("forces", F[:, atoms], Fo[:, atoms], scale, tol)
     mask = np.ones(F.shape[1], dtype=bool)
     mask[atoms] = False
     assert np.all(F[:, mask] == 0.0), "forces written outside the CV atoms"
+    return ratio
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -316,9 +317,10 @@ def test_c3_bias_force_all_walkers(c3, prec):
     assert np.abs(s[0] - so[0]).max() < 1e-12
     assert np.abs(_wrap_torsion_diff(s[1], so[1])).max() < 1e-12
     tol = tol_for(prec)
-    check_bound("C3 V", host(V), Vo, A0, tol)
-    check_bound("C3 dVds", host(dV), dVo, A, tol)
-    check_forces(wk, dw, ref, A, gabs)
+    rv = check_bound("C3 V", host(V), Vo, A0, tol)
+    rg = check_bound("C3 dVds", host(dV), dVo, A, tol)
+    rf = check_forces(wk, dw, ref, A, gabs)
+    print(f"C3 prec={prec}: error / bound: V {rv:.3e}, dV/ds {rg:.3e}, forces {rf:.3e} (bound {tol:g})")
 
 
 def test_c3_cv_compute(c3):
