@@ -85,7 +85,7 @@ def cpu_baseline(spec, hills, q, target_s=20.0):
     import numpy as np
     import oracle
     nq = q.shape[1]
-    probe = 64
+    probe = 2048
     idx = np.linspace(0, nq - 1, probe).astype(np.int64)
     t0 = time.perf_counter()
     oracle.hill_sum(spec, hills.centers, hills.heights, q[:, idx])
