@@ -482,6 +482,99 @@ def test_rmsd_cv_paper_benchmark_shape():
 
 
 # ---------------------------------------------------------------------------
+# the general chain-rule path: atoms shared between COM/RMSD lists, and lists
+# longer than the per-block entry cache (768 entries)
+# ---------------------------------------------------------------------------
+def _general_walkers(seed, nw, n_atoms, na, nb, shared, kinds):
+    """Walkers whose CV lists share atoms. kinds: (CV0, CV1) with CV0 a COM
+    distance between groups A (na atoms) and B (nb atoms) that share `shared`
+    atoms, and CV1 a torsion of 4 atoms from A or an offset RMSD over the
+    atoms of B (reference = positions + U[-0.3, 0.3])."""
+    rng = np.random.default_rng(seed)
+    total = nw * n_atoms
+    pos = rng.uniform(0.0, 6.0, (3, total)).astype(np.float32)
+    mass = W.ATOM_MASSES[rng.integers(0, len(W.ATOM_MASSES), total)].astype(np.float32)
+    lists = [[], [], [], []]
+    refs = []
+    for w in range(nw):
+        perm = rng.permutation(n_atoms)
+        A = np.sort(perm[:na])
+        B = np.sort(np.concatenate([perm[na:na + nb - shared], A[:shared]]))
+        lists[0].append(A.astype(np.int32))
+        lists[1].append(B.astype(np.int32))
+        if kinds[1] == W.CV_TORSION:
+            lists[2].append(rng.choice(A, 4, replace=False).astype(np.int32))
+        else:
+            lists[2].append(B.astype(np.int32))
+            g = w * n_atoms + B
+            refs.append(np.vstack([pos[0][g], pos[1][g], pos[2][g]]).astype(np.float64)
+                        + rng.uniform(-0.3, 0.3, (3, B.size)))
+        lists[3].append(np.zeros(0, np.int32))
+    off = np.zeros((2, 2, nw + 1), dtype=np.int64)
+    chunks, base = [], 0
+    for gi in range(4):
+        o = W._csr(lists[gi]) + base
+        off[gi // 2, gi % 2] = o
+        base = int(o[-1])
+        chunks.extend(lists[gi])
+    idx = np.concatenate(chunks).astype(np.int32)
+    ref = np.zeros((3, idx.size), np.float32)
+    if refs:
+        start = int(off[1, 0, 0])
+        ref[:, start:start + sum(r.shape[1] for r in refs)] = np.concatenate(refs, axis=1)
+    return W.Walkers(n_atoms=np.full(nw, n_atoms, np.int32), atom_base=np.arange(nw, dtype=np.int64) * n_atoms,
+                     x=pos[0].copy(), y=pos[1].copy(), z=pos[2].copy(), mass=mass,
+                     kinds=np.array(kinds, dtype=np.int32), list_off=off.astype(np.int32), list_idx=idx,
+                     ref_x=ref[0].copy(), ref_y=ref[1].copy(), ref_z=ref[2].copy())
+
+
+GENERAL_CASES = [
+    # shared COM atoms, short lists (cached entries, general chain rule)
+    ("shared", 11, 24, 3000, 60, 300, 20, (W.CV_COM_DIST, W.CV_TORSION)),
+    # lists longer than the entry cache (re-gathered entries)
+    ("long", 12, 6, 9000, 500, 2500, 0, (W.CV_COM_DIST, W.CV_TORSION)),
+    # shared atoms between a COM group and an RMSD list, long lists
+    ("rmsd", 13, 6, 9000, 400, 1200, 100, (W.CV_COM_DIST, W.CV_RMSD_OFF)),
+]
+
+
+@pytest.mark.parametrize("name,seed,nw,n_atoms,na,nb,shared,kinds", GENERAL_CASES)
+@pytest.mark.parametrize("shape", ["fused", "split", "grid"])
+def test_general_chain_rule_paths(name, seed, nw, n_atoms, na, nb, shared, kinds, shape, monkeypatch):
+    device()
+    wk = _general_walkers(seed, nw, n_atoms, na, nb, shared, kinds)
+    rng = np.random.default_rng(seed + 100)
+    if kinds[1] == W.CV_TORSION:
+        spec = W.BiasSpec(ndim=2, periodic=(0, 1), lo=(0.0, -PI), hi=(1.5, PI), width=(0.1, 0.3), grid_n=(128, 128))
+        cen = np.vstack([rng.uniform(0.0, 1.0, 3000), rng.uniform(-PI, PI, 3000)])
+    else:
+        spec = W.BiasSpec(ndim=2, periodic=(0, 0), lo=(0.0, 0.0), hi=(1.5, 4.0), width=(0.1, 0.2), grid_n=(128, 128))
+        cen = np.vstack([rng.uniform(0.0, 1.0, 3000), rng.uniform(0.0, 3.0, 3000)])
+    hills = W.Hills(cen, rng.uniform(0.1, 1.2, 3000))
+    ctx = make_ctx(spec, hills)
+    if shape != "grid":
+        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+    dw = abp.DeviceWalkers(wk)
+    mode = abp.ABP_EVAL_GRID if shape == "grid" else abp.ABP_EVAL_DIRECT
+    s, V, dV = abp.bias_force(ctx, dw, mode=mode)
+    abp.abp_sync(ctx)
+    z = np.zeros(wk.total_atoms)
+    H = abp.abp_grid_export(ctx) if shape == "grid" else None
+    ref = oracle.bias_force(spec, hills.centers, hills.heights, wk, z, z, z, use_grid=H is not None, H=H)
+    assert np.all(ref[6] == 0)
+    s = host(s)
+    assert np.abs(s[0] - ref[0][0]).max() < 1e-12
+    d1 = s[1] - ref[0][1]
+    if spec.periodic[1]:
+        d1 = _wrap_torsion_diff(s[1], ref[0][1])
+    assert np.abs(d1).max() < 1e-12
+    _, _, A0, A = oracle.hill_sum(spec, hills.centers, hills.heights, ref[0])
+    check_bound(f"{name} V", host(V), ref[1], A0)
+    check_bound(f"{name} dV", host(dV), ref[2], A)
+    check_forces(wk, dw, ref, A, cv_atom_grad_abs(wk, ref[0]))
+
+
+# ---------------------------------------------------------------------------
 # the paper's quantised grid mode: hills moved to their nearest node, compact
 # stencils on a 480 x 480 grid over [0, 12] nm, force by look-up at the node
 # ---------------------------------------------------------------------------
