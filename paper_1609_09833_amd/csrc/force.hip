@@ -89,6 +89,8 @@ struct FArgs {
   int32_t pmax;                // chunk partials per walker in the workspace (for nvis = committed)
   CvState* state;              // [nw]                 split shape only
   Entry* entries;              // [nw][kMaxCached]     split shape only
+  double* scv;                 // [3][nw] coordinates the sum uses (split shape)
+  int* sbad;                   // [nw] nonzero: walker invalid (split shape)
   float2* part32;              // [nw][pmax][D+1] partial sums (hi, lo), FP32 modes
   double* part64;              // the same buffer, FP64 mode
 };
@@ -370,7 +372,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   if (S.bad) {
     if (tid == 0) {
       atomicOr(A.err, S.bad);
-      if (to_state) F.state[w].bad = S.bad;
+      if (to_state) { F.state[w].bad = S.bad; F.sbad[w] = S.bad; }
     }
     return false;
   }
@@ -444,7 +446,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   if (acc[9 * D] != 0.0) {
     if (tid == 0) {
       atomicOr(A.err, S.bad ? S.bad : kErrIndex);
-      if (to_state) F.state[w].bad = S.bad ? S.bad : kErrIndex;
+      if (to_state) { F.state[w].bad = S.bad ? S.bad : kErrIndex; F.sbad[w] = F.state[w].bad; }
     }
     return false;
   }
@@ -528,7 +530,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   if (S.bad) {
     if (tid == 0) {
       atomicOr(A.err, S.bad);
-      if (to_state) F.state[w].bad = S.bad;
+      if (to_state) { F.state[w].bad = S.bad; F.sbad[w] = S.bad; }
     }
     return false;
   }
@@ -692,6 +694,8 @@ __global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
     const int* src = reinterpret_cast<const int*>(&S);
     int* dst = reinterpret_cast<int*>(F.state + w);
     for (int i = tid; i < kStateWords; i += kFBlock) dst[i] = src[i];
+    if (tid < D) F.scv[tid * A.nw + w] = eval_coord(F.K, tid, S.s[tid]);
+    if (tid == 0) F.sbad[w] = 0;
     Entry* out = F.entries + w * (int64_t)kMaxCached;
 #pragma unroll
     for (int k = 0; k < kCache; ++k)
@@ -777,9 +781,10 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
 
 // ---------------------------------------------------------------------------
 // Split shape, sum launch: one wave per (chunk c, 64 walkers). The chunk's
-// hill indices are wave-uniform, so the records come through the scalar
-// cache, fetched once per 64 walkers; a lane whose walker sees fewer hills
-// masks the rest.
+// 64 hill records are loaded once per wave (one per lane, coalesced) into
+// LDS and read back as broadcasts, so each record is fetched once per 64
+// walkers; a lane whose walker sees fewer hills masks the rest. The walkers'
+// CV values come from a compact [D][nw] array (coalesced).
 // ---------------------------------------------------------------------------
 template <int D, int PMASK, int KERN, bool FP64>
 __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
@@ -792,7 +797,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
   const bool active = w < A.nw;
   const int64_t wc = active ? w : A.nw - 1;
   const int64_t nvis = walker_nvis(F, wc);
-  const bool wanted = active && c * kChunkHills < nvis && !F.state[wc].bad;
+  const bool wanted = active && c * kChunkHills < nvis && !F.sbad[wc];
   if (!__any(wanted)) return;
   const int nmine = wanted ? chunk_terms(nvis, c) : 0;
   const int nrun = chunk_terms(F.committed, c);                 // uniform, >= nmine
@@ -800,14 +805,19 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
   const int64_t k0 = c * kChunkHills;
   double s[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) s[a] = eval_coord(K, a, F.state[wc].s[a]);
+  for (int a = 0; a < D; ++a) s[a] = F.scv[a * A.nw + wc];
   float ph[N], pl[N];
   double pv[N];
+  // the chunk's records, one coalesced load per lane, then LDS broadcasts
+  static_assert(kChunkHills == 64, "one record per lane");
   if constexpr (FP64) {
+    __shared__ double4 tile64[kChunkHills];
+    tile64[lane] = lane < nrun ? hill64(F, D, k0 + lane) : make_double4(0.0, 0.0, 0.0, 0.0);
+    __syncthreads();
     double tq[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) tq[i] = work64(K, i, s[i]);
-    auto ld = [&](int64_t k) { return hill64(F, D, k); };
+    auto ld = [&](int64_t k) { return tile64[k - k0]; };
     if (full) partial_f64<D, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
     else partial_f64<D, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
   } else {
@@ -820,16 +830,10 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
       ua[i] = K.ua32[i];
     }
     const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
-    typedef const __attribute__((address_space(4))) int cint_t;   // uniform loads via the scalar cache
-    cint_t* srec = (cint_t*)F.H.rec32;
-    auto lds = [&](int64_t k) {
-      int4 h;
-      h.x = srec[4 * k];
-      h.y = D > 1 ? srec[4 * k + 1] : 0;
-      h.z = D > 2 ? srec[4 * k + 2] : 0;
-      h.w = srec[4 * k + 3];
-      return h;
-    };
+    __shared__ int4 tile32[kChunkHills];
+    tile32[lane] = lane < nrun ? F.H.rec32[k0 + lane] : make_int4(0, 0, 0, 0);
+    __syncthreads();
+    auto lds = [&](int64_t k) { return tile32[k - k0]; };
     if (full) partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, k0, nrun, nrun, lds, ph, pl);
     else partial_f32<D, PMASK, KERN, true>(qw, kf, ua, K.pl32, comp, k0, nrun, nmine, lds, ph, pl);
   }
@@ -854,7 +858,7 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
   const ForceArgs& A = F.A;
   const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
-  if (F.state[w].bad) return;
+  if (F.sbad[w]) return;
   const int64_t nch = force_chunks(walker_nvis(F, w));
   __shared__ double red[(kFBlock / 64) * 2 * N];
   __shared__ CvState S;
@@ -980,7 +984,8 @@ size_t force_workspace_bytes(int64_t nw, int nbw, int ndim) {
   const size_t st = (size_t)nw * sizeof(CvState);
   const size_t en = (size_t)nw * kMaxCached * sizeof(Entry);
   const size_t pa = (size_t)nw * (size_t)nbw * (size_t)(ndim + 1) * 8;   // float2 or double
-  return (st + 255) / 256 * 256 + (en + 255) / 256 * 256 + pa;
+  const size_t sc = (size_t)nw * (3 * sizeof(double) + sizeof(int));
+  return (st + 255) / 256 * 256 + (en + 255) / 256 * 256 + (sc + 255) / 256 * 256 + pa;
 }
 
 hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* workspace,
@@ -994,6 +999,8 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
   F.pmax = force_blocks_per_walker(F.committed, A.use_grid, A.cv_only);
   F.state = nullptr;
   F.entries = nullptr;
+  F.scv = nullptr;
+  F.sbad = nullptr;
   F.part32 = nullptr;
   F.part64 = nullptr;
   const bool split = force_uses_workspace(A.nw, F.committed, A.use_grid, A.cv_only);
@@ -1002,10 +1009,13 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
     char* p = static_cast<char*>(workspace);
     const size_t st = ((size_t)A.nw * sizeof(CvState) + 255) / 256 * 256;
     const size_t en = ((size_t)A.nw * kMaxCached * sizeof(Entry) + 255) / 256 * 256;
+    const size_t sc = ((size_t)A.nw * (3 * sizeof(double) + sizeof(int)) + 255) / 256 * 256;
     F.state = reinterpret_cast<CvState*>(p);
     F.entries = reinterpret_cast<Entry*>(p + st);
-    F.part32 = reinterpret_cast<float2*>(p + st + en);
-    F.part64 = reinterpret_cast<double*>(p + st + en);
+    F.scv = reinterpret_cast<double*>(p + st + en);
+    F.sbad = reinterpret_cast<int*>(p + st + en + (size_t)A.nw * 3 * sizeof(double));
+    F.part32 = reinterpret_cast<float2*>(p + st + en + sc);
+    F.part64 = reinterpret_cast<double*>(p + st + en + sc);
   }
   int mask = 0;
   for (int i = 0; i < K.ndim; ++i) mask |= (K.periodic[i] ? 1 : 0) << i;
