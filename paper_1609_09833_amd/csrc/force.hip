@@ -786,63 +786,77 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
 // walkers; a lane whose walker sees fewer hills masks the rest. The walkers'
 // CV values come from a compact [D][nw] array (coalesced).
 // ---------------------------------------------------------------------------
+#ifndef ABP_SUM_CPW
+#define ABP_SUM_CPW 1
+#endif
+constexpr int kChunksPerWave = ABP_SUM_CPW;   // consecutive chunks one wave sums (its fixed costs amortised)
+
 template <int D, int PMASK, int KERN, bool FP64>
 __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const Consts& K = F.K;
   const int lane = threadIdx.x;
-  const int64_t c = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kChunksPerWave;
   const int64_t w = (int64_t)blockIdx.y * 64 + lane;
   const bool active = w < A.nw;
   const int64_t wc = active ? w : A.nw - 1;
   const int64_t nvis = walker_nvis(F, wc);
-  const bool wanted = active && c * kChunkHills < nvis && !F.sbad[wc];
-  if (!__any(wanted)) return;
-  const int nmine = wanted ? chunk_terms(nvis, c) : 0;
-  const int nrun = chunk_terms(F.committed, c);                 // uniform, >= nmine
-  const bool full = __all(!wanted || nmine == nrun);
-  const int64_t k0 = c * kChunkHills;
+  const bool alive = active && c0 * kChunkHills < nvis && !F.sbad[wc];
+  if (!__any(alive)) return;
   double s[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) s[a] = F.scv[a * A.nw + wc];
-  float ph[N], pl[N];
-  double pv[N];
-  // the chunk's records, one coalesced load per lane, then LDS broadcasts
+  const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
+  // the chunks' records, one coalesced load per lane per chunk, then LDS broadcasts
   static_assert(kChunkHills == 64, "one record per lane");
-  if constexpr (FP64) {
-    __shared__ double4 tile64[kChunkHills];
-    tile64[lane] = lane < nrun ? hill64(F, D, k0 + lane) : make_double4(0.0, 0.0, 0.0, 0.0);
-    __syncthreads();
-    double tq[D];
+  __shared__ int4 tile32[FP64 ? 1 : kChunksPerWave * kChunkHills];
+  __shared__ double4 tile64[FP64 ? kChunksPerWave * kChunkHills : 1];
 #pragma unroll
-    for (int i = 0; i < D; ++i) tq[i] = work64(K, i, s[i]);
-    auto ld = [&](int64_t k) { return tile64[k - k0]; };
-    if (full) partial_f64<D, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
-    else partial_f64<D, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
-  } else {
-    uint32_t qw[D];
-    float kf[D], ua[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      qw[i] = work32(K, i, s[i]);
-      kf[i] = K.kf32[i];
-      ua[i] = K.ua32[i];
-    }
-    const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
-    __shared__ int4 tile32[kChunkHills];
-    tile32[lane] = lane < nrun ? F.H.rec32[k0 + lane] : make_int4(0, 0, 0, 0);
-    __syncthreads();
-    auto lds = [&](int64_t k) { return tile32[k - k0]; };
-    if (full) partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, k0, nrun, nrun, lds, ph, pl);
-    else partial_f32<D, PMASK, KERN, true>(qw, kf, ua, K.pl32, comp, k0, nrun, nmine, lds, ph, pl);
+  for (int j = 0; j < kChunksPerWave; ++j) {
+    const int64_t k = (c0 + j) * kChunkHills + lane;
+    if constexpr (FP64) tile64[j * kChunkHills + lane] = k < F.committed ? hill64(F, D, k) : make_double4(0.0, 0.0, 0.0, 0.0);
+    else tile32[j * kChunkHills + lane] = k < F.committed ? F.H.rec32[k] : make_int4(0, 0, 0, 0);
   }
-  if (wanted) {
-    const int64_t at = (w * F.pmax + c) * N;
+  __syncthreads();
+  double tq[D];
+  uint32_t qw[D];
+  float kf[D], ua[D];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-      if constexpr (FP64) F.part64[at + r] = pv[r];
-      else F.part32[at + r] = make_float2(ph[r], pl[r]);
+  for (int i = 0; i < D; ++i) {
+    tq[i] = work64(K, i, s[i]);
+    qw[i] = work32(K, i, s[i]);
+    kf[i] = K.kf32[i];
+    ua[i] = K.ua32[i];
+  }
+  const int64_t kbase = c0 * kChunkHills;
+  for (int j = 0; j < kChunksPerWave; ++j) {
+    const int64_t c = c0 + j;
+    if (c >= F.pmax) break;                                      // uniform
+    const bool wanted = active && c * kChunkHills < nvis && !F.sbad[wc];
+    if (!__any(wanted)) break;                                   // later chunks are further out
+    const int nmine = wanted ? chunk_terms(nvis, c) : 0;
+    const int nrun = chunk_terms(F.committed, c);               // uniform, >= nmine
+    const bool full = __all(!wanted || nmine == nrun);
+    const int64_t k0 = c * kChunkHills;
+    float ph[N], pl[N];
+    double pv[N];
+    if constexpr (FP64) {
+      auto ld = [&](int64_t k) { return tile64[k - kbase]; };
+      if (full) partial_f64<D, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
+      else partial_f64<D, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
+    } else {
+      auto lds = [&](int64_t k) { return tile32[k - kbase]; };
+      if (full) partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, k0, nrun, nrun, lds, ph, pl);
+      else partial_f32<D, PMASK, KERN, true>(qw, kf, ua, K.pl32, comp, k0, nrun, nmine, lds, ph, pl);
+    }
+    if (wanted) {
+      const int64_t at = (w * F.pmax + c) * N;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        if constexpr (FP64) F.part64[at + r] = pv[r];
+        else F.part32[at + r] = make_float2(ph[r], pl[r]);
+      }
     }
   }
 }
@@ -919,7 +933,7 @@ hipError_t go_direct(const FArgs& F, bool fused, hipStream_t stream) {
   }
   hipLaunchKernelGGL((k_cv_stage<D, kStageSum>), walkers, dim3(kFBlock), 0, stream, F);
   if (F.pmax > 0) {
-    const dim3 grid((unsigned)F.pmax, (unsigned)((F.A.nw + 63) / 64));
+    const dim3 grid((unsigned)((F.pmax + kChunksPerWave - 1) / kChunksPerWave), (unsigned)((F.A.nw + 63) / 64));
     hipLaunchKernelGGL((k_sum_parts<D, PMASK, KERN, FP64>), grid, dim3(64), 0, stream, F);
   }
   hipLaunchKernelGGL((k_finish_stage<D, FP64>), walkers, dim3(kFBlock), 0, stream, F);
