@@ -201,18 +201,26 @@ abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* wa
 
 /* The whole bias-force step for a batch of walkers: CVs -> bias and
  * gradient at s (DIRECT: hills [0, n_visible[w]), or all committed hills if
- * n_visible is NULL; GRID: interpolation) -> transform -> chain rule
- * F_j += -sum_a dV/ds_a ds_a/dx_j on the CV atoms only ("Minimization of
- * Interprocess Communications": only CV atoms are read and written).
- * One launch for the grid form and for histories of up to 16,384 hills,
- * three launches (CV, hill sum, finish) for longer ones; the environment
- * variable ABP_FORCE_SHAPE=fused|split forces one or the other. A walker's
- * result is bitwise the same in any batch and either shape.
- * Writes s[ncv][nw], V[nw], dVds[ncv][nw] (FP64).
+ * n_visible is NULL, a value outside [0, committed] also meaning all; GRID:
+ * interpolation, or the nearest-node look-up in the quantised mode) ->
+ * transform -> chain rule F_j += -sum_a dV/ds_a ds_a/dx_j on the CV atoms
+ * only ("Minimization of Interprocess Communications": only CV atoms are read
+ * and written; forces are added to the caller's arrays).
+ * Writes s[ncv][nw], V[nw], dVds[ncv][nw] (FP64, device arrays). A walker
+ * whose lists break abp_cv_desc's rules or whose CV atoms hold non-finite
+ * values is skipped (outputs and forces untouched) and flags the error word;
+ * the other walkers are unaffected.
  * deposit_slot (optional, [nw]): if deposit_slot[w] >= 0, the hill centred at
- * walker w's s with height deposit_height[w] (NULL: 1.0; times exp(-V[w]/wt_dT)
- * when wt_dT > 0) is written to that history slot, which must have been
- * reserved with abp_reserve and is made visible by abp_commit. Atom lists must follow abp_cv_desc's rules. */
+ * walker w's s (its nearest node in the quantised mode) with height
+ * deposit_height[w] (NULL: 1.0; times exp(-V[w]/wt_dT) when wt_dT > 0) is
+ * written to that history slot, which must have been reserved with
+ * abp_reserve and is made visible by abp_commit.
+ * Launches: one for the grid form and for histories of up to 16,384 hills;
+ * three (CV, hill sum, finish) for longer ones, which use a workspace the
+ * context allocates on first need (the environment variable
+ * ABP_FORCE_SHAPE=fused|split forces one shape). A walker's result is bitwise
+ * the same in any batch and either shape. Once the workspace exists the call
+ * enqueues kernels only, so it can be captured in a HIP graph. */
 abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
                       const abp_walkers* walkers, const int64_t* n_visible,
                       const int64_t* deposit_slot, const double* deposit_height,
