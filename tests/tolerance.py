@@ -98,3 +98,79 @@ def fp32_kernel_condition(spec, centers, heights, q, snap=None, chunk=512):
         for k in range(d):
             C[k, j0:j0 + chunk] = (np.abs(w)[None, :] * np.abs(der[k]) * kappa).sum(axis=1)
     return C0, C
+
+
+def rounding_error_scales(spec, centers, heights, q, unit, coord_unit, snap=None, chunk=256):
+    """Absolute error estimates (E0 for h, E_i for dh/ds_i) of a sum whose
+    terms are evaluated in a format with unit roundoff `unit`, from the
+    conditioning of each term, before the transform:
+
+      * the exponent: a relative error `unit` in the exponent's argument
+        changes a term by |argument| * unit; the argument is
+        |ln w| + sum_i d_i^2/(2 sigma_i^2) (Gaussian) or
+        |ln w| + sum_i p u_i^2/(1 - u_i^2) with u = |d|/a (compact), and
+        the compact argument's own sensitivity to u adds 2p u^2/(1-u^2)^2;
+      * the coordinates: each query and centre coordinate is rounded with
+        `coord_unit` relative error on non-periodic axes (on periodic axes the
+        fixed-point working form is exact to 2^-32 of the period), which
+        moves d_i by coord_unit (|q_i| + |c_i|) and changes the value by that
+        times |dK/dd_i| and the gradient by that times |d^2K/dd_i^2|.
+
+    Each term's estimate is multiplied by 4 (several roundings per term).
+    Returns (E0[nq], E[ndim][nq]).
+    """
+    q = np.asarray(q, dtype=np.float64)
+    d, nq = q.shape
+    c = np.asarray(centers, dtype=np.float64).reshape(d, -1)
+    w = np.asarray(heights, dtype=np.float64)
+    E0 = np.zeros(nq)
+    E = np.zeros((d, nq))
+    if w.size == 0:
+        return E0, E
+    if snap is not None:
+        q = np.array([[snap(i, x) for x in q[i]] for i in range(d)])
+        c = np.array([[snap(i, x) for x in c[i]] for i in range(d)])
+    p = spec.p
+    lnw = np.abs(np.log(np.where(w > 0, w, 1.0)))[None, :]
+    for j0 in range(0, nq, chunk):
+        qq = q[:, j0:j0 + chunk]
+        m = qq.shape[1]
+        val = np.ones((m, c.shape[1]))
+        arg = np.tile(lnw, (m, 1))
+        dlog = []          # d ln K / d d_i per axis
+        d2 = []            # (d^2 K / d d_i^2) / K per axis
+        ecoord = []
+        for i in range(d):
+            delta = qq[i][:, None] - c[i][None, :]
+            if spec.periodic[i]:
+                L = spec.hi[i] - spec.lo[i]
+                delta = delta - L * np.round(delta / L)
+                ec = np.zeros_like(delta)
+            else:
+                ec = coord_unit * (np.abs(qq[i])[:, None] + np.abs(c[i])[None, :])
+            a = spec.width[i]
+            if spec.kernel == 0:
+                s = np.exp(-0.5 * (delta / a) ** 2)
+                arg = arg + 0.5 * (delta / a) ** 2
+                g = -delta / a ** 2
+                h2 = (delta ** 2 / a ** 2 - 1.0) / a ** 2
+            else:
+                u = np.abs(delta) / a
+                inside = u < 1.0
+                om = np.where(inside, 1.0 - u * u, 1.0)
+                s = np.where(inside, np.exp(-p * u * u / om), 0.0)
+                arg = arg + np.where(inside, p * u * u / om + 2.0 * p * u * u / (om * om), 0.0)
+                g = np.where(inside, -2.0 * p * delta / (a * a * om * om), 0.0)
+                h2 = np.where(inside, g * g + np.abs(2.0 * p * (1.0 + 3.0 * u * u) / (a * a * om ** 3)), 0.0)
+            val = val * s
+            dlog.append(g)
+            d2.append(np.abs(h2))
+            ecoord.append(ec)
+        wk = np.abs(w)[None, :] * val
+        rel = unit * arg
+        E0[j0:j0 + m] = 4.0 * (wk * (rel + sum(np.abs(dlog[i]) * ecoord[i] for i in range(d)))).sum(axis=1)
+        for k in range(d):
+            gk = wk * np.abs(dlog[k])
+            extra = sum((d2[i] if i == k else np.abs(dlog[i]) * np.abs(dlog[k])) * ecoord[i] for i in range(d))
+            E[k, j0:j0 + m] = 4.0 * (gk * rel + wk * extra).sum(axis=1)
+    return E0, E
