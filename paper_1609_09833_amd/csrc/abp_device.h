@@ -125,8 +125,37 @@ __device__ __forceinline__ void kahan_fold(float (&S)[N], float (&C)[N], const f
   }
 }
 
-// One hill against one query, FP64. tc/tq are work64 coordinates; w the height.
-template <int D, int KERN>
+// log2 of a hill height as the FP64 sums read it (heights are finite and >= 0).
+__device__ __forceinline__ double log2_height(double w) { return w > 0.0 ? log2(w) : kLog2Zero; }
+
+// 2^x for the FP64 hill terms: x = k + r with k = rint(x), |r| <= 1/2
+// (exact); 2^r from the degree-11 Chebyshev interpolant of 2^r on
+// [-1/2, 1/2] in the monomial basis (relative error below 5e-18 before
+// rounding; csrc/exp2_poly.py computes the coefficients), then scaled by 2^k.
+// x is clamped below at -1100, where the result is already exactly 0, so a
+// -inf argument (an infinitely distant hill) also gives 0. x is never above
+// log2 of the largest height (< 1024), so k fits an int. A NaN argument is
+// not propagated; the kernels mark results for non-finite queries themselves.
+constexpr double kExp2Poly[12] = {1.0, 0.6931471805599453, 0.2402265069591016, 0.05550410866482084,
+                                  0.00961812910758714, 0.0013333558146525846, 0.00015403530463787193,
+                                  1.5252733768382024e-05, 1.3215432523120778e-06, 1.0178076233676354e-07,
+                                  7.074195451650667e-09, 4.454084508627905e-10};
+
+__device__ __forceinline__ double exp2_term(double x) {
+  x = fmax(x, -1100.0);
+  const double k = rint(x);
+  const double r = x - k;
+  double p = kExp2Poly[11];
+#pragma unroll
+  for (int n = 10; n >= 0; --n) p = __builtin_fma(p, r, kExp2Poly[n]);
+  return ldexp(p, (int)k);
+}
+
+// One hill against one query, FP64. tq and h.x..h.z are work64 coordinates,
+// h.w is log2 of the height (folded into the exponent, as in the FP32 path).
+// PMASK selects the periodic axes (minimum image); ISO: every axis has the
+// same exponent factor kf64[0].
+template <int D, int PMASK, int KERN, bool ISO = false>
 __device__ __forceinline__ void pair64(const Consts& K, const double (&tq)[D], const double4& h,
                                        double (&P)[D + 1]) {
   double d[D];
@@ -134,14 +163,21 @@ __device__ __forceinline__ void pair64(const Consts& K, const double (&tq)[D], c
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     double x = tq[i] - hc[i];
-    x -= K.per64[i] * rint(x);
+    if ((PMASK >> i) & 1) x -= rint(x);       // periodic coordinates are in periods
     d[i] = x;
   }
   if (KERN == ABP_K_GAUSS) {
-    double a = 0.0;
+    double a = h.w;
+    if (ISO) {
+      double t = d[0] * d[0];
 #pragma unroll
-    for (int i = 0; i < D; ++i) a = __builtin_fma(d[i] * K.kf64[i], d[i], a);
-    const double we = h.w * exp2(-a);
+      for (int i = 1; i < D; ++i) t = __builtin_fma(d[i], d[i], t);
+      a = __builtin_fma(-K.kf64[0], t, a);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) a = __builtin_fma(-d[i] * K.kf64[i], d[i], a);
+    }
+    const double we = exp2_term(a);
     P[0] += we;
 #pragma unroll
     for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fma(we, d[i], P[i + 1]);
@@ -157,7 +193,7 @@ __device__ __forceinline__ void pair64(const Consts& K, const double (&tq)[D], c
       a = __builtin_fma(t, r, a);
       f[i] = u * r * r;
     }
-    const double we = inside ? h.w * exp2(-K.pl64 * a) : 0.0;
+    const double we = inside ? exp2_term(__builtin_fma(-K.pl64, a, h.w)) : 0.0;
     P[0] += we;
 #pragma unroll
     for (int i = 0; i < D; ++i) P[i + 1] = __builtin_fma(we, f[i], P[i + 1]);

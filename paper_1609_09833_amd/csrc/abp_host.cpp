@@ -23,6 +23,7 @@ struct abp_ctx {
   int64_t reserved = 0;       // slots handed out (>= committed)
   double* c64 = nullptr;
   double* w64 = nullptr;
+  double* l64 = nullptr;
   int4* rec32 = nullptr;
   double* grid = nullptr;
   int32_t* err = nullptr;
@@ -38,6 +39,7 @@ struct abp_ctx {
     HistView h;
     h.c64 = c64;
     h.w64 = w64;
+    h.l64 = l64;
     h.rec32 = rec32;
     h.capacity = desc.capacity;
     return h;
@@ -258,6 +260,7 @@ abp_status grid_add(abp_ctx* ctx, int64_t k0, int64_t k1, hipStream_t stream) {
 void free_all(abp_ctx* ctx) {
   if (ctx->c64) (void)hipFree(ctx->c64);
   if (ctx->w64) (void)hipFree(ctx->w64);
+  if (ctx->l64) (void)hipFree(ctx->l64);
   if (ctx->rec32) (void)hipFree(ctx->rec32);
   if (ctx->grid) (void)hipFree(ctx->grid);
   if (ctx->err) (void)hipFree(ctx->err);
@@ -293,6 +296,7 @@ abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out) {
   const int64_t cap = desc->capacity;
   bool good = hipMalloc(&ctx->c64, sizeof(double) * desc->ndim * cap) == hipSuccess &&
               hipMalloc(&ctx->w64, sizeof(double) * cap) == hipSuccess &&
+              hipMalloc(&ctx->l64, sizeof(double) * cap) == hipSuccess &&
               hipMalloc(&ctx->rec32, sizeof(int4) * cap) == hipSuccess &&
               hipMalloc(&ctx->err, sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&ctx->clamped, sizeof(unsigned long long)) == hipSuccess;

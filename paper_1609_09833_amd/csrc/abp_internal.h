@@ -22,6 +22,10 @@ constexpr int kTile64 = 512;     // hills per LDS tile in the FP64 direct sum (1
 constexpr int kChunk = ABP_CHUNK; // hills summed plainly before each compensated (Kahan) step
 constexpr int kQ2D = ABP_Q2D;     // queries per thread in the 2-D/3-D FP32 direct sum
 
+// log2 of a zero height in the FP64 sums: finite, so that the exponent of a
+// term stays finite, and far enough below -1074 that the term is exactly 0.
+constexpr double kLog2Zero = -2048.0;
+
 // Device error word bits.
 enum : int32_t { kErrIndex = 1 << 0, kErrNonfinite = 1 << 1, kErrInval = 1 << 2 };
 
@@ -59,6 +63,7 @@ struct Consts {
 struct HistView {
   double* c64;      // [ndim][capacity] master centers
   double* w64;      // [capacity] master heights
+  double* l64;      // [capacity] log2 of the heights (kLog2Zero for a zero height), read by the FP64 sums
   int4* rec32;      // [capacity] FP32 working records {c0, c1, c2, log2(w)}
   int64_t capacity;
 };

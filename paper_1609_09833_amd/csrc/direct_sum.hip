@@ -7,14 +7,19 @@
 namespace abp {
 namespace {
 
-template <int D, int KERN>
+template <int D, int PMASK, int KERN, bool ISO>
 __global__ __launch_bounds__(kBlock) void k_direct_f64(const DirectArgs A) {
   __shared__ double4 tile[kTile64];
   const int64_t iq0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t iq = iq0 < A.nq ? iq0 : A.nq - 1;
   double tq[D], P[D + 1];
+  bool finite = true;
 #pragma unroll
-  for (int i = 0; i < D; ++i) tq[i] = work64(A.K, i, eval_coord(A.K, i, load_q(A, i, iq)));
+  for (int i = 0; i < D; ++i) {
+    const double x = load_q(A, i, iq);
+    finite = finite && isfinite(x);
+    tq[i] = work64(A.K, i, eval_coord(A.K, i, x));
+  }
 #pragma unroll
   for (int r = 0; r <= D; ++r) P[r] = 0.0;
   for (int64_t t0 = 0; t0 < A.nvis; t0 += kTile64) {
@@ -26,29 +31,53 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(const DirectArgs A) {
       r.x = work64(A.K, 0, A.c64[k]);
       r.y = D > 1 ? work64(A.K, 1, A.c64[A.capacity + k]) : 0.0;
       r.z = D > 2 ? work64(A.K, 2, A.c64[2 * A.capacity + k]) : 0.0;
-      r.w = A.w64[k];
+      r.w = A.l64[k];
       tile[i] = r;
     }
     __syncthreads();
-    for (int c = 0; c < n; ++c) pair64<D, KERN>(A.K, tq, tile[c], P);
+    for (int c = 0; c < n; ++c) pair64<D, PMASK, KERN, ISO>(A.K, tq, tile[c], P);
   }
   double dh[D], V, dV[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) dh[i] = P[i + 1] * A.K.gs64[i];
   apply_transform<D>(A.K, P[0], dh, V, dV);
+  if (!finite) {                       // the terms clamp their exponents; say so here
+    V = __builtin_nan("");
+#pragma unroll
+    for (int i = 0; i < D; ++i) dV[i] = V;
+  }
   if (iq0 < A.nq) store_out<D>(A, iq0, V, dV);
 }
 
-template <int D, int KERN>
+template <int D, int PMASK, int KERN, bool ISO>
 hipError_t go_f64(const DirectArgs& A, hipStream_t stream) {
   const int64_t blocks = (A.nq + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_direct_f64<D, KERN>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, A);
+  hipLaunchKernelGGL((k_direct_f64<D, PMASK, KERN, ISO>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, A);
   return hipGetLastError();
 }
 
+template <int D, int PMASK>
+hipError_t dispatch_f64_mask(const DirectArgs& A, bool iso, hipStream_t stream) {
+  if (A.K.kernel != ABP_K_GAUSS) return go_f64<D, PMASK, ABP_K_COMPACT, false>(A, stream);
+  if constexpr (D > 1 && (PMASK == 0 || PMASK == (1 << D) - 1))
+    if (iso) return go_f64<D, PMASK, ABP_K_GAUSS, true>(A, stream);
+  return go_f64<D, PMASK, ABP_K_GAUSS, false>(A, stream);
+}
+
 template <int D>
-hipError_t dispatch_f64(const DirectArgs& A, hipStream_t stream) {
-  return A.K.kernel == ABP_K_GAUSS ? go_f64<D, ABP_K_GAUSS>(A, stream) : go_f64<D, ABP_K_COMPACT>(A, stream);
+hipError_t dispatch_f64(const DirectArgs& A, int mask, bool iso, hipStream_t stream) {
+  switch (mask) {
+    case 0: return dispatch_f64_mask<D, 0>(A, iso, stream);
+    case 1: return dispatch_f64_mask<D, 1>(A, iso, stream);
+    case 2: if constexpr (D >= 2) return dispatch_f64_mask<D, 2>(A, iso, stream); break;
+    case 3: if constexpr (D >= 2) return dispatch_f64_mask<D, 3>(A, iso, stream); break;
+    case 4: if constexpr (D >= 3) return dispatch_f64_mask<D, 4>(A, iso, stream); break;
+    case 5: if constexpr (D >= 3) return dispatch_f64_mask<D, 5>(A, iso, stream); break;
+    case 6: if constexpr (D >= 3) return dispatch_f64_mask<D, 6>(A, iso, stream); break;
+    case 7: if constexpr (D >= 3) return dispatch_f64_mask<D, 7>(A, iso, stream); break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -61,7 +90,7 @@ hipError_t launch_direct_sum(const Consts& K, const HistView& H, int64_t n_visib
   A.K = K;
   A.rec32 = H.rec32;
   A.c64 = H.c64;
-  A.w64 = H.w64;
+  A.l64 = H.l64;
   A.capacity = H.capacity;
   A.nvis = n_visible;
   A.nq = nq;
@@ -70,16 +99,17 @@ hipError_t launch_direct_sum(const Consts& K, const HistView& H, int64_t n_visib
   A.dV = dVds;
   A.q_f64 = q_f64;
   int mask = 0;
-  bool iso = K.kernel == ABP_K_GAUSS;
+  bool iso = K.kernel == ABP_K_GAUSS, iso64 = iso;
   for (int i = 0; i < K.ndim; ++i) {
     mask |= (K.periodic[i] ? 1 : 0) << i;
     iso = iso && K.kf32[i] == K.kf32[0];
+    iso64 = iso64 && K.kf64[i] == K.kf64[0];
   }
   if (prec == ABP_PREC_FP64) {
     switch (K.ndim) {
-      case 1: return dispatch_f64<1>(A, stream);
-      case 2: return dispatch_f64<2>(A, stream);
-      case 3: return dispatch_f64<3>(A, stream);
+      case 1: return dispatch_f64<1>(A, mask, iso64, stream);
+      case 2: return dispatch_f64<2>(A, mask, iso64, stream);
+      case 3: return dispatch_f64<3>(A, mask, iso64, stream);
       default: return hipErrorInvalidValue;
     }
   }

@@ -26,7 +26,7 @@ struct DirectArgs {
   Consts K;
   const int4* rec32;
   const double* c64;
-  const double* w64;
+  const double* l64;      // log2 of the heights (FP64 path)
   int64_t capacity;
   int64_t nvis;
   int64_t nq;

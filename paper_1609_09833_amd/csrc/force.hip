@@ -204,6 +204,7 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
     words[a] = work32(F.K, a, c);
   }
   F.H.w64[slot] = hw;
+  F.H.l64[slot] = log2_height(hw);
   int4 rec;
   rec.x = (int)words[0];
   rec.y = (int)words[1];
@@ -611,7 +612,7 @@ __device__ __forceinline__ void partial_f32(const uint32_t (&qw)[D], const float
 }
 
 // One chunk sum (FP64), same terms; zero-height terms add exact zeros.
-template <int D, int KERN, bool MASK, class Load>
+template <int D, int PMASK, int KERN, bool MASK, class Load>
 __device__ __forceinline__ void partial_f64(const Consts& K, const double (&tq)[D], int64_t k0, int nrun,
                                             int nmine, Load load, double (&v)[D + 1]) {
   double Pp[D + 1];
@@ -619,8 +620,8 @@ __device__ __forceinline__ void partial_f64(const Consts& K, const double (&tq)[
   for (int r = 0; r <= D; ++r) Pp[r] = 0.0;
   for (int u = 0; u < nrun; ++u) {
     double4 hr = load(k0 + u);
-    if (MASK && u >= nmine) hr.w = 0.0;
-    pair64<D, KERN>(K, tq, hr, Pp);
+    if (MASK && u >= nmine) hr.w = kLog2Zero;
+    pair64<D, PMASK, KERN>(K, tq, hr, Pp);
   }
 #pragma unroll
   for (int r = 0; r <= D; ++r) v[r] = Pp[r];
@@ -631,7 +632,7 @@ __device__ __forceinline__ double4 hill64(const FArgs& F, int D, int64_t k) {
   hr.x = work64(F.K, 0, F.H.c64[k]);
   hr.y = D > 1 ? work64(F.K, 1, F.H.c64[F.H.capacity + k]) : 0.0;
   hr.z = D > 2 ? work64(F.K, 2, F.H.c64[2 * F.H.capacity + k]) : 0.0;
-  hr.w = F.H.w64[k];
+  hr.w = F.H.l64[k];
   return hr;
 }
 
@@ -751,7 +752,7 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
     for (int64_t c = tid; c < nch; c += kFBlock) {
       const int n = chunk_terms(nvis, c);
       double pv[N];
-      partial_f64<D, KERN, false>(K, tq, c * kChunkHills, n, n, [&](int64_t k) { return hill64(F, D, k); }, pv);
+      partial_f64<D, PMASK, KERN, false>(K, tq, c * kChunkHills, n, n, [&](int64_t k) { return hill64(F, D, k); }, pv);
       const float z[N] = {};
       merge_part<N, true>(hi, lo, v64, z, z, pv, comp);
     }
@@ -815,7 +816,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
 #pragma unroll
   for (int j = 0; j < kChunksPerWave; ++j) {
     const int64_t k = (c0 + j) * kChunkHills + lane;
-    if constexpr (FP64) tile64[j * kChunkHills + lane] = k < F.committed ? hill64(F, D, k) : make_double4(0.0, 0.0, 0.0, 0.0);
+    if constexpr (FP64) tile64[j * kChunkHills + lane] = k < F.committed ? hill64(F, D, k) : make_double4(0.0, 0.0, 0.0, kLog2Zero);
     else tile32[j * kChunkHills + lane] = k < F.committed ? F.H.rec32[k] : make_int4(0, 0, 0, 0);
   }
   __syncthreads();
@@ -843,8 +844,8 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
     double pv[N];
     if constexpr (FP64) {
       auto ld = [&](int64_t k) { return tile64[k - kbase]; };
-      if (full) partial_f64<D, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
-      else partial_f64<D, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
+      if (full) partial_f64<D, PMASK, KERN, false>(K, tq, k0, nrun, nrun, ld, pv);
+      else partial_f64<D, PMASK, KERN, true>(K, tq, k0, nrun, nmine, ld, pv);
     } else {
       auto lds = [&](int64_t k) { return tile32[k - kbase]; };
       if (full) partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, k0, nrun, nrun, lds, ph, pl);
@@ -940,17 +941,17 @@ hipError_t go_direct(const FArgs& F, bool fused, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int D, int KERN>
+template <int D, int KERN, bool FP64>
 hipError_t direct_by_mask(int mask, const FArgs& F, bool fused, hipStream_t stream) {
   switch (mask) {
-    case 0: return go_direct<D, 0, KERN, false>(F, fused, stream);
-    case 1: return go_direct<D, 1, KERN, false>(F, fused, stream);
-    case 2: if constexpr (D >= 2) return go_direct<D, 2, KERN, false>(F, fused, stream); break;
-    case 3: if constexpr (D >= 2) return go_direct<D, 3, KERN, false>(F, fused, stream); break;
-    case 4: if constexpr (D >= 3) return go_direct<D, 4, KERN, false>(F, fused, stream); break;
-    case 5: if constexpr (D >= 3) return go_direct<D, 5, KERN, false>(F, fused, stream); break;
-    case 6: if constexpr (D >= 3) return go_direct<D, 6, KERN, false>(F, fused, stream); break;
-    case 7: if constexpr (D >= 3) return go_direct<D, 7, KERN, false>(F, fused, stream); break;
+    case 0: return go_direct<D, 0, KERN, FP64>(F, fused, stream);
+    case 1: return go_direct<D, 1, KERN, FP64>(F, fused, stream);
+    case 2: if constexpr (D >= 2) return go_direct<D, 2, KERN, FP64>(F, fused, stream); break;
+    case 3: if constexpr (D >= 2) return go_direct<D, 3, KERN, FP64>(F, fused, stream); break;
+    case 4: if constexpr (D >= 3) return go_direct<D, 4, KERN, FP64>(F, fused, stream); break;
+    case 5: if constexpr (D >= 3) return go_direct<D, 5, KERN, FP64>(F, fused, stream); break;
+    case 6: if constexpr (D >= 3) return go_direct<D, 6, KERN, FP64>(F, fused, stream); break;
+    case 7: if constexpr (D >= 3) return go_direct<D, 7, KERN, FP64>(F, fused, stream); break;
     default: break;
   }
   return hipErrorInvalidValue;
@@ -969,10 +970,10 @@ hipError_t launch_d(int mask, const FArgs& F, bool fused, hipStream_t stream) {
   }
   const bool gauss = F.K.kernel == ABP_K_GAUSS;
   if (F.A.prec == ABP_PREC_FP64)
-    return gauss ? go_direct<D, 0, ABP_K_GAUSS, true>(F, fused, stream)
-                 : go_direct<D, 0, ABP_K_COMPACT, true>(F, fused, stream);
-  return gauss ? direct_by_mask<D, ABP_K_GAUSS>(mask, F, fused, stream)
-               : direct_by_mask<D, ABP_K_COMPACT>(mask, F, fused, stream);
+    return gauss ? direct_by_mask<D, ABP_K_GAUSS, true>(mask, F, fused, stream)
+                 : direct_by_mask<D, ABP_K_COMPACT, true>(mask, F, fused, stream);
+  return gauss ? direct_by_mask<D, ABP_K_GAUSS, false>(mask, F, fused, stream)
+               : direct_by_mask<D, ABP_K_COMPACT, false>(mask, F, fused, stream);
 }
 
 }  // namespace

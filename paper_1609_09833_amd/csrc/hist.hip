@@ -51,6 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_append(const AppendArgs A) {
     words[i] = work32(A.K, i, c[i]);
   }
   A.H.w64[slot] = w;
+  A.H.l64[slot] = log2_height(w);
   rec.x = (int)words[0];
   rec.y = (int)words[1];
   rec.z = (int)words[2];
@@ -65,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_init(const HistView H, int ndim
   if (k >= H.capacity) return;
   for (int i = 0; i < ndim; ++i) H.c64[i * H.capacity + k] = 0.0;
   H.w64[k] = 0.0;
+  H.l64[k] = kLog2Zero;
   int4 rec;
   rec.x = 0;
   rec.y = 0;
