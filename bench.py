@@ -423,16 +423,23 @@ def main():
         el2, _ = timed(fn, steps, 1, stream)
         extra[name] = {"walker_steps_per_s": nq * steps / el2, "ms_per_step": el2 / steps * 1e3}
         log(f"bench: {name} {nq * steps / el2:.4e} walker-steps/s")
-    # grid: accumulate 50,000 hills into a 256^2 FP64 grid, then interpolate at all queries
-    gctx = abp.Context(spec, capacity=nh)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    abp.bias_deposit(gctx, cen_d, hts_d)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    extra["grid_build_ms"] = e0.elapsed_time(e1)
+    # grid: accumulate 50,000 hills into a 256^2 FP64 grid, then interpolate at all queries.
+    # A context's first deposit also allocates the deposit's split scratch, so the build
+    # time reported is a second deposit of the same 50,000 hills into the same context.
+    gctx = abp.Context(spec, capacity=2 * nh)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        abp.bias_deposit(gctx, cen_d, hts_d)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    abp.abp_sync(gctx)
+    extra["grid_build_ms"] = times[1]
+    extra["grid_build_first_call_ms"] = times[0]
     del build_s
 
     def grid_step():

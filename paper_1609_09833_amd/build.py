@@ -28,6 +28,12 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+# Per-source flags. grid.hip: the MFMA deposit keeps its accumulators in
+# ordinary VGPRs (the VGPR form of the MFMA instructions); with AGPR
+# accumulators the compiler copies all of them in and out on every iteration.
+EXTRA = {"grid.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     out = []
     for name in sorted(os.listdir(CSRC)):
@@ -38,7 +44,7 @@ def sources():
 
 def _compile(src, build_dir=BUILD, extra=()):
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the packed-fp32 feature and says so; drop that line
     noise = "is not a recognized feature for this target"

@@ -218,9 +218,19 @@ template <int D>
 __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const Entry (&ent)[kCache]) {
   const int tid = threadIdx.x;
   if (S.fast) {
+    // Every cached COM/RMSD entry is a distinct atom here (no atom is in two
+    // such lists and each list is strictly increasing), so all the old forces
+    // can be read before any is written back: one round trip per thread
+    // instead of one per entry.
+    double add[kCache][3];
+    int64_t gat[kCache];
+    bool live[kCache];
 #pragma unroll
     for (int k = 0; k < kCache; ++k) {
       const Entry en = ent[k];
+      live[k] = false;
+      gat[k] = 0;
+      add[k][0] = add[k][1] = add[k][2] = 0.0;
       if (en.gi < 0) continue;
       const int a = en.li >> 1, t = en.li & 1;
       const int kind = S.kind[a];
@@ -252,9 +262,27 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
             S.tclaimed[b2][j] = 1;
           }
       }
-      rmw_force(A.fx, gi, fx);
-      rmw_force(A.fy, gi, fy);
-      rmw_force(A.fz, gi, fz);
+      live[k] = true;
+      gat[k] = gi;
+      add[k][0] = fx;
+      add[k][1] = fy;
+      add[k][2] = fz;
+    }
+    float old[kCache][3];
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) {
+      old[k][0] = old[k][1] = old[k][2] = 0.0f;
+      if (!live[k]) continue;
+      old[k][0] = A.fx[gat[k]];
+      old[k][1] = A.fy[gat[k]];
+      old[k][2] = A.fz[gat[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) {
+      if (!live[k]) continue;
+      A.fx[gat[k]] = (float)((double)old[k][0] + add[k][0]);
+      A.fy[gat[k]] = (float)((double)old[k][1] + add[k][1]);
+      A.fz[gat[k]] = (float)((double)old[k][2] + add[k][2]);
     }
     __syncthreads();
     // torsion atoms in no COM/RMSD list: the first torsion occurrence writes the total

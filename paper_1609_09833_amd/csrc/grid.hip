@@ -9,12 +9,14 @@
 // quantised mode reads the value and first-derivative arrays at the nearest
 // node instead (the paper's look-up).
 //
-// The hill is a product over axes, so per hill and per node tile the block
-// evaluates 1-D factor vectors once (LDS) and forms the node values as
-// outer products: each node costs 2^ndim FMAs per hill. Each thread owns
-// COLS x RY nodes of the tile, so one LDS read of a factor pair feeds several
-// FMAs. For compact kernels a hill whose support misses the tile is skipped,
-// which is the Nbase^d saving of eq. Cupdate at tile granularity.
+// The hill is a product over axes, so the node arrays of a batch are sums of
+// outer products of 1-D factor vectors: each node costs 2^ndim FMAs per hill.
+// For 2-D Gaussian grids that sum is a dense contraction over the hills and
+// runs on the matrix cores (FP64 MFMA, k_deposit_mfma2). Otherwise a block
+// evaluates the 1-D factors of a chunk of hills once (LDS) and each thread
+// forms COLS x RY nodes from them; for compact kernels a hill whose support
+// misses the tile is skipped, which is the Nbase^d saving of eq. Cupdate at
+// tile granularity.
 //
 // Evaluation: one thread per query, 2^ndim corners x 2^ndim arrays gathered
 // from the node-interleaved layout, FP64 arithmetic.
@@ -23,14 +25,13 @@
 namespace abp {
 namespace {
 
-// Tile shape: 64 * COLS nodes along axis 0 (lane l owns columns l, l + 64,
-// ...), 4 * RY along axis 1 (wave v owns rows v*RY ..), one plane along axis
-// 2. Gaussian hills cover every node, so wide 2-D tiles spread each hill's
-// factor evaluations over more nodes; a compact hill touches few nodes, so
-// its tiles stay narrow (less work on the nodes outside its support).
-template <int D, bool WIDE> struct TileShape { static constexpr int COLS = 1, RY = 8; };
-template <> struct TileShape<2, true> { static constexpr int COLS = 2, RY = 8; };
-constexpr int kKC = 16;        // hills per LDS chunk
+// Tile shape of the VALU deposit (compact 2-D hills, all 3-D grids): 64 * COLS
+// nodes along axis 0 (lane l owns columns l, l + 64, ...), 4 * RY along axis
+// 1 (wave v owns rows v*RY ..), one plane along axis 2. Narrow tiles keep the
+// work on nodes outside a compact hill's support small. 2-D Gaussian grids
+// use the matrix-core deposit below.
+constexpr int kCols = 1, kRY = 8;   // nodes per thread: columns x rows
+constexpr int kKC = 16;             // hills per LDS chunk
 constexpr int kMinBlocks = 1024;
 
 struct DepositArgs {
@@ -45,20 +46,23 @@ struct DepositArgs {
   double* scratch;         // [nsplit][nodes][2^D] when nsplit > 1
 };
 
-// Value and derivative (d/ds) of axis `i` of hill centred at c, at node coordinate x.
+constexpr double kHalfLog2e = 0.72134752044448170368;   // log2(e) / 2
+
+// Value and derivative (d/ds) of axis `i` of hill centred at c, at node
+// coordinate x (exponentials through the FP64 hill-term exp2).
 __device__ __forceinline__ void factor(const Consts& K, int i, double x, double c, double& v, double& d) {
   double delta = x - c;
   if (K.periodic[i]) delta -= K.period[i] * rint(delta * K.inv_period[i]);
   const double iw = K.inv_width[i];
   if (K.kernel == ABP_K_GAUSS) {
     const double r = delta * iw;
-    v = exp(-0.5 * r * r);
+    v = exp2_term(-kHalfLog2e * (r * r));
     d = -(r * iw) * v;
   } else {
     const double u = delta * iw;
     if (fabs(u) < 1.0) {
       const double ro = 1.0 / (1.0 - u * u);
-      v = exp(-(double)K.p * u * u * ro);
+      v = exp2_term(-K.pl64 * (u * u * ro));
       d = -2.0 * K.p * u * iw * ro * ro * v;
     } else {
       v = 0.0;
@@ -106,11 +110,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit_1d(const DepositArgs A) {
 }
 
 // 2-D and 3-D grids: tile of 64*COLS x 4*RY nodes (one z plane for 3-D).
-template <int D, bool WIDE>
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
   constexpr int NM = 1 << D;
   constexpr int NY = 1 << (D - 1);          // combos of the derivative bits of axes 1..D-1
-  constexpr int COLS = TileShape<D, WIDE>::COLS, RY = TileShape<D, WIDE>::RY;
+  constexpr int COLS = kCols, RY = kRY;
   constexpr int TX = 64 * COLS, TY = 4 * RY;
   __shared__ double2 Xf[kKC][TX];           // axis-0 (value, derivative) at the tile's columns
   __shared__ double Yf[kKC][TY][NY];        // w * (axis 1 x axis 2 factors)
@@ -221,6 +225,120 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
   }
 }
 
+// 2-D Gaussian grids on the matrix cores. For one hill sub-range the node
+// arrays are sums of outer products, H_m[y][x] = sum_k (w_k Y_my(y; c_k))
+// (X_mx(x; c_k)), i.e. four FP64 matrix products (m = mx + 2 my) with the
+// hills as the contraction index. One wave owns a 32 x 32 node tile (2 x 2
+// tiles of 16 x 16 for v_mfma_f64_16x16x4f64) and walks its hills four at a
+// time: lane l supplies the factors of hill l / 16 at node row / column
+// l % 16, computed in registers (no LDS, no barriers), and the next group's
+// factors are formed while the current group's products run.
+// Operand layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16 x 4, B 4 x 16):
+// A[i][k] and B[k][j] sit in lane i + 16 k and j + 16 k; D[i][j] in lane
+// j + 16 (i % 4), register i / 4.
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int kMT = 32;              // nodes per side of a wave's tile
+constexpr int kMinWaves = 4096;      // target waves per deposit launch (4 per SIMD)
+
+// Gaussian factor of axis i (periodic when P) at node coordinate x for a hill
+// centred at c: value v and d/ds derivative d (straight-line code).
+template <bool P>
+__device__ __forceinline__ void gauss_factor(const Consts& K, int i, double x, double c, double& v, double& d) {
+  double delta = x - c;
+  if (P) delta -= K.period[i] * rint(delta * K.inv_period[i]);
+  const double iw = K.inv_width[i];
+  const double r = delta * iw;
+  v = exp2_term(-kHalfLog2e * (r * r));
+  d = -(r * iw) * v;
+}
+
+template <int PMASK>
+__global__ __launch_bounds__(64) void k_deposit_mfma2(const DepositArgs A) {
+  const Consts& K = A.K;
+  const int64_t n0 = K.grid_n[0], n1 = K.grid_n[1];
+  const int64_t tiles_x = (n0 + kMT - 1) / kMT;
+  const int64_t tile = blockIdx.x % A.tiles;
+  const int s = (int)(blockIdx.x / A.tiles);
+  const int64_t x0 = (tile % tiles_x) * kMT, y0 = (tile / tiles_x) * kMT;
+  const int lane = threadIdx.x;
+  const int kk = lane >> 4, i16 = lane & 15;
+  int64_t kb, ke;
+  split_range(A, s, kb, ke);
+  if (ke <= kb) return;
+
+  double yc[2], xc[2];
+  bool yin[2], xin[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t yj = y0 + 16 * t + i16, xj = x0 + 16 * t + i16;
+    yin[t] = yj < n1;
+    xin[t] = xj < n0;
+    yc[t] = node_coord(K, 1, yin[t] ? yj : 0);
+    xc[t] = node_coord(K, 0, xin[t] ? xj : 0);
+  }
+  // factors of hill k0 + lane / 16: ya[my][t] (A operands, y rows, times w)
+  // and xb[mx][t] (B operands, x columns); zero outside the grid or the range
+  // (a hill index past the range reads the range's last hill with weight 0)
+  auto operands = [&](int64_t k0, double (&ya)[2][2], double (&xb)[2][2]) {
+    const int64_t k = k0 + kk;
+    const int64_t kc = k < ke ? k : ke - 1;
+    const double c0 = A.c64[kc], c1 = A.c64[A.capacity + kc], wk = A.w64[kc];
+    const double w = k < ke ? wk : 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      double v, d;
+      gauss_factor<(PMASK & 2) != 0>(K, 1, yc[t], c1, v, d);
+      ya[0][t] = yin[t] ? w * v : 0.0;
+      ya[1][t] = yin[t] ? w * d : 0.0;
+      gauss_factor<(PMASK & 1) != 0>(K, 0, xc[t], c0, v, d);
+      xb[0][t] = xin[t] ? v : 0.0;
+      xb[1][t] = xin[t] ? d : 0.0;
+    }
+  };
+  d4v acc[2][2][4];
+#pragma unroll
+  for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+    for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[ty][tx][m] = d4v{0.0, 0.0, 0.0, 0.0};
+  double ya[2][2], xb[2][2];
+  operands(kb, ya, xb);
+  for (int64_t k0 = kb; k0 < ke; k0 += 4) {
+#pragma unroll
+    for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+      for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+        for (int my = 0; my < 2; ++my)
+#pragma unroll
+          for (int mx = 0; mx < 2; ++mx)
+            acc[ty][tx][mx + 2 * my] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(ya[my][ty], xb[mx][tx], acc[ty][tx][mx + 2 * my], 0, 0, 0);
+    operands(k0 + 4, ya, xb);     // the next group (weight 0 past the range)
+  }
+  // lane holds x column x0 + 16 tx + lane % 16 and y rows y0 + 16 ty + 4 r + lane / 16
+#pragma unroll
+  for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+    for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t xj = x0 + 16 * tx + i16, yj = y0 + 16 * ty + 4 * r + kk;
+        if (xj >= n0 || yj >= n1) continue;
+        const int64_t node = xj + n0 * yj;
+        if (A.nsplit == 1) {
+          double* g = A.grid + node * 4;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) g[m] += acc[ty][tx][m][r];
+        } else {
+          double* o = A.scratch + ((int64_t)s * K.nodes + node) * 4;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) o[m] = acc[ty][tx][m][r];
+        }
+      }
+}
+
 // grid[v] += sum over split s (in order) of scratch[s][v].
 __global__ __launch_bounds__(kBlock) void k_reduce_split(double* grid, const double* scratch,
                                                          int64_t nvals, int nsplit) {
@@ -282,23 +400,27 @@ __global__ __launch_bounds__(kBlock) void k_grid_eval(const EvalArgs A) {
   }
 }
 
-template <int D, bool WIDE>
+template <int D>
 int64_t tiles_of(const Consts& K) {
-  constexpr int TX = 64 * TileShape<D, WIDE>::COLS, TY = 4 * TileShape<D, WIDE>::RY;
+  constexpr int TX = 64 * kCols, TY = 4 * kRY;
   int64_t t = ((K.grid_n[0] + TX - 1) / TX) * ((K.grid_n[1] + TY - 1) / TY);
   if (D == 3) t *= K.grid_n[2];
   return t;
 }
 
+bool uses_mfma(const Consts& K) { return K.ndim == 2 && K.kernel == ABP_K_GAUSS; }
+
 int64_t node_tiles(const Consts& K) {
   if (K.ndim == 1) return (K.grid_n[0] + kBlock - 1) / kBlock;
-  if (K.ndim == 3) return tiles_of<3, false>(K);
-  return K.kernel == ABP_K_GAUSS ? tiles_of<2, true>(K) : tiles_of<2, false>(K);
+  if (K.ndim == 3) return tiles_of<3>(K);
+  if (uses_mfma(K)) return ((K.grid_n[0] + kMT - 1) / kMT) * ((K.grid_n[1] + kMT - 1) / kMT);
+  return tiles_of<2>(K);
 }
 
 int split_for(const Consts& K, int64_t nhills) {
   const int64_t tiles = node_tiles(K);
-  int64_t s = (kMinBlocks + tiles - 1) / tiles;
+  const int64_t want = uses_mfma(K) ? kMinWaves : kMinBlocks;
+  int64_t s = (want + tiles - 1) / tiles;
   const int64_t by_hills = nhills / 256;       // at least 256 hills per sub-range
   if (s > by_hills) s = by_hills;
   if (s < 1) s = 1;
@@ -333,10 +455,16 @@ hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, i
   switch (K.ndim) {
     case 1: hipLaunchKernelGGL(k_deposit_1d, dim3(blocks), dim3(kBlock), 0, stream, A); break;
     case 2:
-      if (K.kernel == ABP_K_GAUSS) hipLaunchKernelGGL((k_deposit_nd<2, true>), dim3(blocks), dim3(kBlock), 0, stream, A);
-      else hipLaunchKernelGGL((k_deposit_nd<2, false>), dim3(blocks), dim3(kBlock), 0, stream, A);
+      if (uses_mfma(K)) {
+        const int pm = (K.periodic[0] ? 1 : 0) | (K.periodic[1] ? 2 : 0);
+        if (pm == 0) hipLaunchKernelGGL(k_deposit_mfma2<0>, dim3(blocks), dim3(64), 0, stream, A);
+        else if (pm == 1) hipLaunchKernelGGL(k_deposit_mfma2<1>, dim3(blocks), dim3(64), 0, stream, A);
+        else if (pm == 2) hipLaunchKernelGGL(k_deposit_mfma2<2>, dim3(blocks), dim3(64), 0, stream, A);
+        else hipLaunchKernelGGL(k_deposit_mfma2<3>, dim3(blocks), dim3(64), 0, stream, A);
+      }
+      else hipLaunchKernelGGL(k_deposit_nd<2>, dim3(blocks), dim3(kBlock), 0, stream, A);
       break;
-    case 3: hipLaunchKernelGGL((k_deposit_nd<3, false>), dim3(blocks), dim3(kBlock), 0, stream, A); break;
+    case 3: hipLaunchKernelGGL(k_deposit_nd<3>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
