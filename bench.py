@@ -35,7 +35,7 @@ FP32_NONPACKED_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12   # FMA on every lane, no 
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE (x 2,
 # copy-calibrated) and WRITE_SIZE (x 1), valid only for the kernel sources
 # they were taken on.
-HEADLINE_TRAFFIC = {"sources_sha256": "b248308aecadd4c2cf386c17c37ea599c6f6a7aab57f04266da51518203f012d", "fetch_kib": 7307.3, "write_kib": 12288.0,
+HEADLINE_TRAFFIC = {"sources_sha256": "f40c5db412823f41384f913c732223498642bd2943d6fc41edbfd96491fa9441", "fetch_kib": 7307.4, "write_kib": 12288.0,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 HEADLINE_SOURCES = ("paper_1609_09833_amd/csrc/direct_sum_impl.h", "paper_1609_09833_amd/csrc/direct_sum_d2.hip",
                     "paper_1609_09833_amd/csrc/direct_sum.hip", "paper_1609_09833_amd/csrc/abp_device.h",
@@ -313,6 +313,38 @@ def serving_leg(abp, W, torch, window_s=1.0):
     return res
 
 
+def grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV):
+    """Grid form on the headline workload: accumulate the 50,000 hills into the
+    256^2 FP64 grid, then interpolate at all 1,048,576 queries. A context's first
+    deposit also allocates the deposit's split scratch, so the build time
+    reported is a second deposit of the same 50,000 hills into the same context."""
+    nq = qd.shape[1]
+    extra = {}
+    gctx = abp.Context(spec, capacity=2 * nh)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        abp.bias_deposit(gctx, cen_d, hts_d)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    abp.abp_sync(gctx)
+    extra["grid_build_ms"] = times[1]
+    extra["grid_build_first_call_ms"] = times[0]
+
+    def grid_step():
+        abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
+    el3, _ = timed(grid_step, args.steps, 2, stream)
+    extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
+                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
+    log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
+    gctx.close()
+    return extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,9 +353,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
-    ap.add_argument("--only", choices=("headline", "force", "latency", "serving", "quantised"), default=None,
-                    help="run one leg only (profiling): the headline direct sum, the fused bias-force "
-                         "workload, or the serving workload")
+    ap.add_argument("--only", choices=("headline", "grid", "force", "latency", "serving", "quantised"), default=None,
+                    help="run one leg only (profiling): the headline direct sum, its grid form, the "
+                         "bias-force workload, single-walker latency, the quantised grid or serving")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -375,6 +407,10 @@ def main():
     qd = torch.as_tensor(q, device=dev)
     V = torch.empty(nq, dtype=torch.float32, device=dev)
     dV = torch.empty((2, nq), dtype=torch.float32, device=dev)
+    if args.only == "grid":
+        print(json.dumps({"extra": grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV)}),
+              flush=True)
+        return
 
     def step_kahan():
         abp.bias_eval(ctx, qd, prec=abp.ABP_PREC_FP32_KAHAN, V=V, dVds=dV)
@@ -423,31 +459,8 @@ def main():
         el2, _ = timed(fn, steps, 1, stream)
         extra[name] = {"walker_steps_per_s": nq * steps / el2, "ms_per_step": el2 / steps * 1e3}
         log(f"bench: {name} {nq * steps / el2:.4e} walker-steps/s")
-    # grid: accumulate 50,000 hills into a 256^2 FP64 grid, then interpolate at all queries.
-    # A context's first deposit also allocates the deposit's split scratch, so the build
-    # time reported is a second deposit of the same 50,000 hills into the same context.
-    gctx = abp.Context(spec, capacity=2 * nh)
-    times = []
-    for _ in range(2):
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        abp.bias_deposit(gctx, cen_d, hts_d)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    abp.abp_sync(gctx)
-    extra["grid_build_ms"] = times[1]
-    extra["grid_build_first_call_ms"] = times[0]
+    extra.update(grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV))
     del build_s
-
-    def grid_step():
-        abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
-    el3, _ = timed(grid_step, args.steps, 2, stream)
-    extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
-                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
-    log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
     extra.update(force_leg(abp, W, torch, args, stream))
     extra["single_walker_latency"] = latency_leg(abp, W, torch)
     extra["quantised_grid"] = quantised_leg(abp, W, torch)
