@@ -239,6 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
 typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kMT = 32;              // nodes per side of a wave's tile
 constexpr int kMinWaves = 4096;      // target waves per deposit launch (4 per SIMD)
+constexpr int kStage = 256;          // hills per LDS chunk of the MFMA deposits
 
 // Gaussian factor of axis i (periodic when P) at node coordinate x for a hill
 // centred at c: value v and d/ds derivative d (straight-line code).
@@ -276,21 +277,17 @@ __global__ __launch_bounds__(64) void k_deposit_mfma2(const DepositArgs A) {
     yc[t] = node_coord(K, 1, yin[t] ? yj : 0);
     xc[t] = node_coord(K, 0, xin[t] ? xj : 0);
   }
-  // factors of hill k0 + lane / 16: ya[my][t] (A operands, y rows, times w)
-  // and xb[mx][t] (B operands, x columns); zero outside the grid or the range
-  // (a hill index past the range reads the range's last hill with weight 0)
-  auto operands = [&](int64_t k0, double (&ya)[2][2], double (&xb)[2][2]) {
-    const int64_t k = k0 + kk;
-    const int64_t kc = k < ke ? k : ke - 1;
-    const double c0 = A.c64[kc], c1 = A.c64[A.capacity + kc], wk = A.w64[kc];
-    const double w = k < ke ? wk : 0.0;
+  // its factors for hill centre (h[0], h[1]) and height h[2]: ya[my][t] (A
+  // operands, y rows, times the height) and xb[mx][t] (B operands, x
+  // columns); zero outside the grid
+  auto factors = [&](const double (&h)[3], double (&ya)[2][2], double (&xb)[2][2]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       double v, d;
-      gauss_factor<(PMASK & 2) != 0>(K, 1, yc[t], c1, v, d);
-      ya[0][t] = yin[t] ? w * v : 0.0;
-      ya[1][t] = yin[t] ? w * d : 0.0;
-      gauss_factor<(PMASK & 1) != 0>(K, 0, xc[t], c0, v, d);
+      gauss_factor<(PMASK & 2) != 0>(K, 1, yc[t], h[1], v, d);
+      ya[0][t] = yin[t] ? h[2] * v : 0.0;
+      ya[1][t] = yin[t] ? h[2] * d : 0.0;
+      gauss_factor<(PMASK & 1) != 0>(K, 0, xc[t], h[0], v, d);
       xb[0][t] = xin[t] ? v : 0.0;
       xb[1][t] = xin[t] ? d : 0.0;
     }
@@ -302,20 +299,36 @@ __global__ __launch_bounds__(64) void k_deposit_mfma2(const DepositArgs A) {
     for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[ty][tx][m] = d4v{0.0, 0.0, 0.0, 0.0};
-  double ya[2][2], xb[2][2];
-  operands(kb, ya, xb);
-  for (int64_t k0 = kb; k0 < ke; k0 += 4) {
+  // The sub-range's hills pass through LDS in chunks of kStage: one coalesced
+  // load per chunk instead of a memory round trip per group of four.
+  __shared__ double hs[3][kStage];
+  for (int64_t c0 = kb; c0 < ke; c0 += kStage) {
+    const int n = (int)(ke - c0 < kStage ? ke - c0 : kStage);
+    __syncthreads();
 #pragma unroll
-    for (int ty = 0; ty < 2; ++ty)
+    for (int j = 0; j < kStage / 64; ++j) {
+      const int u = lane + 64 * j;
+      const int64_t k = c0 + (u < n ? u : n - 1);
+      hs[0][u] = A.c64[k];
+      hs[1][u] = A.c64[A.capacity + k];
+      hs[2][u] = u < n ? A.w64[k] : 0.0;          // past the range: weight 0
+    }
+    __syncthreads();
+    for (int g = 0; g < n; g += 4) {
+      const double h[3] = {hs[0][g + kk], hs[1][g + kk], hs[2][g + kk]};
+      double ya[2][2], xb[2][2];
+      factors(h, ya, xb);
 #pragma unroll
-      for (int tx = 0; tx < 2; ++tx)
+      for (int ty = 0; ty < 2; ++ty)
 #pragma unroll
-        for (int my = 0; my < 2; ++my)
+        for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
-          for (int mx = 0; mx < 2; ++mx)
-            acc[ty][tx][mx + 2 * my] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(ya[my][ty], xb[mx][tx], acc[ty][tx][mx + 2 * my], 0, 0, 0);
-    operands(k0 + 4, ya, xb);     // the next group (weight 0 past the range)
+          for (int my = 0; my < 2; ++my)
+#pragma unroll
+            for (int mx = 0; mx < 2; ++mx)
+              acc[ty][tx][mx + 2 * my] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(ya[my][ty], xb[mx][tx], acc[ty][tx][mx + 2 * my], 0, 0, 0);
+    }
   }
   // lane holds x column x0 + 16 tx + lane % 16 and y rows y0 + 16 ty + 4 r + lane / 16
 #pragma unroll
@@ -337,6 +350,112 @@ __global__ __launch_bounds__(64) void k_deposit_mfma2(const DepositArgs A) {
           for (int m = 0; m < 4; ++m) o[m] = acc[ty][tx][m][r];
         }
       }
+}
+
+// 3-D Gaussian grids on the matrix cores: per z plane, H_m[z][y][x] =
+// sum_k (w_k Y_my(y) Z_mz(z)) X_mx(x) with m = mx + 2 my + 4 mz, eight FP64
+// matrix products per plane. One wave owns a 16 (y) x 32 (x) node tile of one
+// plane; lane l supplies hill l / 16's factors at row / column l % 16 (the
+// z factor at the plane's coordinate), as in k_deposit_mfma2.
+constexpr int kMT3Y = 16;            // y rows of a 3-D wave tile (x columns: kMT)
+
+template <int PMASK>
+__global__ __launch_bounds__(64) void k_deposit_mfma3(const DepositArgs A) {
+  const Consts& K = A.K;
+  const int64_t n0 = K.grid_n[0], n1 = K.grid_n[1];
+  const int64_t tiles_x = (n0 + kMT - 1) / kMT, tiles_y = (n1 + kMT3Y - 1) / kMT3Y;
+  const int64_t tile = blockIdx.x % A.tiles;
+  const int s = (int)(blockIdx.x / A.tiles);
+  const int64_t x0 = (tile % tiles_x) * kMT, y0 = ((tile / tiles_x) % tiles_y) * kMT3Y;
+  const int64_t z = tile / (tiles_x * tiles_y);
+  const int lane = threadIdx.x;
+  const int kk = lane >> 4, i16 = lane & 15;
+  int64_t kb, ke;
+  split_range(A, s, kb, ke);
+  if (ke <= kb) return;
+
+  const int64_t yj = y0 + i16;
+  const bool yin = yj < n1;
+  const double yc = node_coord(K, 1, yin ? yj : 0), zc = node_coord(K, 2, z);
+  double xc[2];
+  bool xin[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t xj = x0 + 16 * t + i16;
+    xin[t] = xj < n0;
+    xc[t] = node_coord(K, 0, xin[t] ? xj : 0);
+  }
+  // its factors for hill centre (h[0], h[1], h[2]) and height h[3]:
+  // ya[my + 2 mz] (A operands, y rows, times the height and the z factor) and
+  // xb[mx][t] (B operands, x columns); zero outside the grid
+  auto factors = [&](const double (&h)[4], double (&ya)[4], double (&xb)[2][2]) {
+    double yv, yd, zv, zd;
+    gauss_factor<(PMASK & 2) != 0>(K, 1, yc, h[1], yv, yd);
+    gauss_factor<(PMASK & 4) != 0>(K, 2, zc, h[2], zv, zd);
+    const double w = yin ? h[3] : 0.0;
+    ya[0] = w * (yv * zv);
+    ya[1] = w * (yd * zv);
+    ya[2] = w * (yv * zd);
+    ya[3] = w * (yd * zd);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      double v, d;
+      gauss_factor<(PMASK & 1) != 0>(K, 0, xc[t], h[0], v, d);
+      xb[0][t] = xin[t] ? v : 0.0;
+      xb[1][t] = xin[t] ? d : 0.0;
+    }
+  };
+  d4v acc[2][8];
+#pragma unroll
+  for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc[tx][m] = d4v{0.0, 0.0, 0.0, 0.0};
+  __shared__ double hs[4][kStage];                // hills staged as in k_deposit_mfma2
+  for (int64_t c0 = kb; c0 < ke; c0 += kStage) {
+    const int n = (int)(ke - c0 < kStage ? ke - c0 : kStage);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kStage / 64; ++j) {
+      const int u = lane + 64 * j;
+      const int64_t k = c0 + (u < n ? u : n - 1);
+      hs[0][u] = A.c64[k];
+      hs[1][u] = A.c64[A.capacity + k];
+      hs[2][u] = A.c64[2 * A.capacity + k];
+      hs[3][u] = u < n ? A.w64[k] : 0.0;          // past the range: weight 0
+    }
+    __syncthreads();
+    for (int g = 0; g < n; g += 4) {
+      const double h[4] = {hs[0][g + kk], hs[1][g + kk], hs[2][g + kk], hs[3][g + kk]};
+      double ya[4], xb[2][2];
+      factors(h, ya, xb);
+#pragma unroll
+      for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+        for (int myz = 0; myz < 4; ++myz)
+#pragma unroll
+          for (int mx = 0; mx < 2; ++mx)
+            acc[tx][mx + 2 * myz] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(ya[myz], xb[mx][tx], acc[tx][mx + 2 * myz], 0, 0, 0);
+    }
+  }
+  // lane holds x column x0 + 16 tx + lane % 16 and y rows y0 + 4 r + lane / 16
+#pragma unroll
+  for (int tx = 0; tx < 2; ++tx)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t xj = x0 + 16 * tx + i16, yr = y0 + 4 * r + kk;
+      if (xj >= n0 || yr >= n1) continue;
+      const int64_t node = xj + n0 * (yr + n1 * z);
+      if (A.nsplit == 1) {
+        double* g = A.grid + node * 8;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) g[m] += acc[tx][m][r];
+      } else {
+        double* o = A.scratch + ((int64_t)s * K.nodes + node) * 8;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) o[m] = acc[tx][m][r];
+      }
+    }
 }
 
 // grid[v] += sum over split s (in order) of scratch[s][v].
@@ -408,13 +527,17 @@ int64_t tiles_of(const Consts& K) {
   return t;
 }
 
-bool uses_mfma(const Consts& K) { return K.ndim == 2 && K.kernel == ABP_K_GAUSS; }
+bool uses_mfma(const Consts& K) { return K.ndim >= 2 && K.kernel == ABP_K_GAUSS; }
 
+// Tiles of the deposit launch for this grid (each kernel's own tile shape).
 int64_t node_tiles(const Consts& K) {
   if (K.ndim == 1) return (K.grid_n[0] + kBlock - 1) / kBlock;
-  if (K.ndim == 3) return tiles_of<3>(K);
-  if (uses_mfma(K)) return ((K.grid_n[0] + kMT - 1) / kMT) * ((K.grid_n[1] + kMT - 1) / kMT);
-  return tiles_of<2>(K);
+  if (uses_mfma(K)) {
+    const int64_t tx = (K.grid_n[0] + kMT - 1) / kMT;
+    if (K.ndim == 3) return tx * ((K.grid_n[1] + kMT3Y - 1) / kMT3Y) * K.grid_n[2];
+    return tx * ((K.grid_n[1] + kMT - 1) / kMT);
+  }
+  return K.ndim == 3 ? tiles_of<3>(K) : tiles_of<2>(K);
 }
 
 int split_for(const Consts& K, int64_t nhills) {
@@ -464,7 +587,23 @@ hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, i
       }
       else hipLaunchKernelGGL(k_deposit_nd<2>, dim3(blocks), dim3(kBlock), 0, stream, A);
       break;
-    case 3: hipLaunchKernelGGL(k_deposit_nd<3>, dim3(blocks), dim3(kBlock), 0, stream, A); break;
+    case 3:
+      if (uses_mfma(K)) {
+        const int pm = (K.periodic[0] ? 1 : 0) | (K.periodic[1] ? 2 : 0) | (K.periodic[2] ? 4 : 0);
+        switch (pm) {
+          case 0: hipLaunchKernelGGL(k_deposit_mfma3<0>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 1: hipLaunchKernelGGL(k_deposit_mfma3<1>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 2: hipLaunchKernelGGL(k_deposit_mfma3<2>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 3: hipLaunchKernelGGL(k_deposit_mfma3<3>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 4: hipLaunchKernelGGL(k_deposit_mfma3<4>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 5: hipLaunchKernelGGL(k_deposit_mfma3<5>, dim3(blocks), dim3(64), 0, stream, A); break;
+          case 6: hipLaunchKernelGGL(k_deposit_mfma3<6>, dim3(blocks), dim3(64), 0, stream, A); break;
+          default: hipLaunchKernelGGL(k_deposit_mfma3<7>, dim3(blocks), dim3(64), 0, stream, A); break;
+        }
+      } else {
+        hipLaunchKernelGGL(k_deposit_nd<3>, dim3(blocks), dim3(kBlock), 0, stream, A);
+      }
+      break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
