@@ -11,8 +11,8 @@
 //
 // The hill is a product over axes, so the node arrays of a batch are sums of
 // outer products of 1-D factor vectors: each node costs 2^ndim FMAs per hill.
-// For 2-D Gaussian grids that sum is a dense contraction over the hills and
-// runs on the matrix cores (FP64 MFMA, k_deposit_mfma2). Otherwise a block
+// For 2-D and 3-D Gaussian grids that sum is a dense contraction over the
+// hills and runs on the matrix cores (FP64 MFMA, k_deposit_mfma2/3). Otherwise a block
 // evaluates the 1-D factors of a chunk of hills once (LDS) and each thread
 // forms COLS x RY nodes from them; for compact kernels a hill whose support
 // misses the tile is skipped, which is the Nbase^d saving of eq. Cupdate at
@@ -25,11 +25,11 @@
 namespace abp {
 namespace {
 
-// Tile shape of the VALU deposit (compact 2-D hills, all 3-D grids): 64 * COLS
+// Tile shape of the VALU deposit (compact 2-D and 3-D hills): 64 * COLS
 // nodes along axis 0 (lane l owns columns l, l + 64, ...), 4 * RY along axis
 // 1 (wave v owns rows v*RY ..), one plane along axis 2. Narrow tiles keep the
-// work on nodes outside a compact hill's support small. 2-D Gaussian grids
-// use the matrix-core deposit below.
+// work on nodes outside a compact hill's support small. Gaussian grids use
+// the matrix-core deposits below.
 constexpr int kCols = 1, kRY = 8;   // nodes per thread: columns x rows
 constexpr int kKC = 16;             // hills per LDS chunk
 constexpr int kMinBlocks = 1024;
