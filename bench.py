@@ -345,6 +345,33 @@ def grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV):
     return extra
 
 
+def stress_grid_leg(abp, W, torch):
+    """The precision-stress grid: 1,000,000 Gaussian hills (a distance and two
+    torsions) into the 128^3 FP64 grid, deposited twice into one context; the
+    reported time is the second deposit (the first also allocates)."""
+    spec, hills, _ = W.stress_3d(n_queries=1)
+    cen = torch.as_tensor(hills.centers, device="cuda")
+    hts = torch.as_tensor(hills.heights, device="cuda")
+    ctx = abp.Context(spec, capacity=2 * hills.n)
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        abp.bias_deposit(ctx, cen, hts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    abp.abp_sync(ctx)
+    ctx.close()
+    flops = 2.0 * 8 * 128 ** 3 * hills.n
+    log(f"bench: stress grid build {times[1]:.1f} ms ({flops / times[1] / 1e9:.1f} TFLOP/s of deposit FMAs)")
+    return {"hills": hills.n, "grid": "128^3 x 8 FP64", "build_ms": times[1], "first_call_ms": times[0],
+            "deposit_tflops": flops / times[1] / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,9 +380,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
-    ap.add_argument("--only", choices=("headline", "grid", "force", "latency", "serving", "quantised"), default=None,
+    ap.add_argument("--only", choices=("headline", "grid", "stress-grid", "force", "latency", "serving",
+                                       "quantised"), default=None,
                     help="run one leg only (profiling): the headline direct sum, its grid form, the "
-                         "bias-force workload, single-walker latency, the quantised grid or serving")
+                         "bias-force workload, single-walker latency, the quantised grid, the 128^3 "
+                         "precision-stress grid build or serving")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -381,6 +410,9 @@ def main():
         return
     if args.only == "quantised":
         print(json.dumps({"extra": {"quantised_grid": quantised_leg(abp, W, torch)}}), flush=True)
+        return
+    if args.only == "stress-grid":
+        print(json.dumps({"extra": {"stress_grid": stress_grid_leg(abp, W, torch)}}), flush=True)
         return
     if args.only == "serving":
         print(json.dumps({"extra": {"serving": serving_leg(abp, W, torch)}}), flush=True)
@@ -464,6 +496,7 @@ def main():
     extra.update(force_leg(abp, W, torch, args, stream))
     extra["single_walker_latency"] = latency_leg(abp, W, torch)
     extra["quantised_grid"] = quantised_leg(abp, W, torch)
+    extra["stress_grid"] = stress_grid_leg(abp, W, torch)
     if not args.no_serving:
         sv = serving_leg(abp, W, torch)
         head = sv["hist200k_budget512MiB"]
