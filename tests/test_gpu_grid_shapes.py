@@ -1,0 +1,93 @@
+"""Grid deposits at edge shapes, against the oracle's grid.
+
+Gaussian 2-D and 3-D grids take the matrix-core deposit (32 x 32 and
+16 x 32 node tiles per wave, hills in groups of four, hill sub-ranges split
+over waves and reduced in order); these cases put tile edges, ragged groups
+and splits where they can go wrong: grids smaller than one tile (down to two nodes per axis) or one node
+past a tile, every periodic mask, hill counts that leave a partial group,
+splits whose sub-ranges are not multiples of four, and a grid built by many
+small deposits (the in-place accumulation path) against one built at once.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_09833_amd import workloads as W
+from tests.gpu_common import device, to_dev
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+def _spec(ndim, periodic, grid_n, kernel=W.KERNEL_GAUSS):
+    lo = tuple(-PI if p else -0.5 for p in periodic)
+    hi = tuple(PI if p else 1.5 for p in periodic)
+    width = tuple(0.4 if p else 0.3 for p in periodic)
+    return W.BiasSpec(ndim=ndim, periodic=periodic, lo=lo, hi=hi, width=width, kernel=kernel, p=3,
+                      grid_n=grid_n)
+
+
+def _hills(spec, n, seed):
+    rng = np.random.default_rng(seed)
+    cen = np.vstack([rng.uniform(spec.lo[i], spec.hi[i], n) for i in range(spec.ndim)])
+    return W.Hills(cen, rng.uniform(0.05, 1.3, n))
+
+
+def _check(spec, H, hills):
+    Ho = oracle.grid_all(spec, hills.centers, hills.heights)
+    np.testing.assert_allclose(H, Ho, rtol=1e-9, atol=1e-12 * max(np.abs(Ho).max(), 1e-300))
+
+
+CASES = [
+    (2, (1, 1), (2, 3)), (2, (0, 0), (2, 2)), (2, (1, 0), (33, 2)), (2, (0, 1), (31, 65)),
+    (2, (1, 1), (64, 32)), (2, (0, 0), (97, 33)),
+    (3, (1, 1, 1), (2, 3, 2)), (3, (0, 0, 0), (2, 2, 2)), (3, (1, 0, 1), (33, 17, 3)),
+    (3, (0, 1, 0), (32, 16, 2)), (3, (0, 0, 1), (31, 15, 5)), (3, (1, 1, 0), (65, 31, 4)),
+]
+
+
+@pytest.mark.parametrize("ndim,periodic,grid_n", CASES)
+@pytest.mark.parametrize("n_hills", [1, 3, 5, 998])
+def test_gauss_grid_edges(ndim, periodic, grid_n, n_hills):
+    device()
+    from paper_1609_09833_amd import abp
+    spec = _spec(ndim, periodic, grid_n)
+    hills = _hills(spec, n_hills, 7 * n_hills + ndim)
+    ctx = abp.Context(spec, capacity=n_hills)
+    abp.bias_deposit(ctx, to_dev(hills.centers), to_dev(hills.heights))
+    abp.abp_sync(ctx)
+    _check(spec, abp.abp_grid_export(ctx), hills)
+
+
+@pytest.mark.parametrize("ndim,grid_n", [(2, (40, 24)), (3, (20, 12, 6))])
+def test_split_ragged_subranges(ndim, grid_n):
+    """16,387 hills on a few tiles: the deposit splits them into many
+    sub-ranges, most not multiples of four, reduced in order."""
+    device()
+    from paper_1609_09833_amd import abp
+    spec = _spec(ndim, (1,) * ndim, grid_n)
+    hills = _hills(spec, 16387, 91 + ndim)
+    ctx = abp.Context(spec, capacity=hills.n)
+    abp.bias_deposit(ctx, to_dev(hills.centers), to_dev(hills.heights))
+    abp.abp_sync(ctx)
+    _check(spec, abp.abp_grid_export(ctx), hills)
+
+
+@pytest.mark.parametrize("ndim,grid_n", [(2, (45, 37)), (3, (19, 17, 3))])
+def test_incremental_deposits_match_one_batch(ndim, grid_n):
+    """Many small deposits (one, then three, then five hills, ...) accumulate
+    in place into the grid; the result matches the oracle for all hills."""
+    device()
+    from paper_1609_09833_amd import abp
+    spec = _spec(ndim, (0,) + (1,) * (ndim - 1), grid_n)
+    hills = _hills(spec, 300, 5 + ndim)
+    ctx = abp.Context(spec, capacity=hills.n)
+    k, step = 0, 1
+    while k < hills.n:
+        m = min(step, hills.n - k)
+        abp.bias_deposit(ctx, to_dev(np.ascontiguousarray(hills.centers[:, k:k + m])),
+                         to_dev(np.ascontiguousarray(hills.heights[k:k + m])))
+        k += m
+        step = step % 7 + 2
+    abp.abp_sync(ctx)
+    _check(spec, abp.abp_grid_export(ctx), hills)
