@@ -40,8 +40,12 @@ __device__ __forceinline__ double snap_index(const Consts& K, int axis, double x
   return fmin(fmax(t, 0.0), n - 1.0);   // (the periodic remainder is already in range)
 }
 
+// lo + j dx with two roundings, as written: contracting it into one fused
+// multiply-add would move nodes by an ulp wherever lo is not 0.
 __device__ __forceinline__ double snap_coord(const Consts& K, int axis, double x) {
-  return __dadd_rn(K.lo[axis], __dmul_rn(snap_index(K, axis, x), K.grid_dx[axis]));
+#pragma clang fp contract(off)
+  const double p = snap_index(K, axis, x) * K.grid_dx[axis];
+  return K.lo[axis] + p;
 }
 
 // The coordinate a sum or deposit uses: x itself, or its node when quantised.

@@ -91,3 +91,21 @@ def test_incremental_deposits_match_one_batch(ndim, grid_n):
         step = step % 7 + 2
     abp.abp_sync(ctx)
     _check(spec, abp.abp_grid_export(ctx), hills)
+
+
+@pytest.mark.parametrize("ndim,grid_n", [(2, (48, 40)), (3, (20, 18, 6))])
+def test_quantised_gauss_grid(ndim, grid_n):
+    """Quantised mode with Gaussian hills: centres snap to their nearest node
+    at deposit, then take the matrix-core deposit like any Gaussian grid."""
+    device()
+    from paper_1609_09833_amd import abp
+    import dataclasses
+    spec = dataclasses.replace(_spec(ndim, (0,) + (1,) * (ndim - 1), grid_n), quantize=1)
+    hills = _hills(spec, 777, 13 + ndim)
+    ctx = abp.Context(spec, capacity=hills.n)
+    abp.bias_deposit(ctx, to_dev(hills.centers), to_dev(hills.heights))
+    abp.abp_sync(ctx)
+    cen, _ = abp.abp_hills_export(ctx)
+    snapped = np.array([[oracle.snap(spec, i, x) for x in hills.centers[i]] for i in range(ndim)])
+    assert np.array_equal(cen, snapped)
+    _check(spec, abp.abp_grid_export(ctx), hills)
