@@ -71,8 +71,12 @@ __device__ __forceinline__ void factor(const Consts& K, int i, double x, double 
   }
 }
 
+// Node j's coordinate, lo + j dx with two roundings (not fused), the same
+// value the quantised mode snaps hill centres and queries to.
 __device__ __forceinline__ double node_coord(const Consts& K, int i, int64_t j) {
-  return K.lo[i] + (double)j * K.grid_dx[i];
+#pragma clang fp contract(off)
+  const double p = (double)j * K.grid_dx[i];
+  return K.lo[i] + p;
 }
 
 __device__ __forceinline__ void split_range(const DepositArgs& A, int s, int64_t& kb, int64_t& ke) {
