@@ -1,7 +1,7 @@
 """Randomised parity sweep: seeded random bias definitions (dimension,
-periodicity, kernel, widths, exponent p, transform, heights including zeros),
-ragged hill and query counts and both I/O dtypes, every precision mode and
-the grid form, each against the FP64 oracle."""
+periodicity, kernel, widths, exponent p, transform, the quantised mode,
+heights including zeros), ragged hill and query counts and both I/O dtypes,
+every precision mode and the grid form, each against the FP64 oracle."""
 import dataclasses
 import math
 
@@ -47,6 +47,12 @@ def _random_case(seed):
     q = np.vstack([rng.uniform(lo[i] - (0 if periodic[i] else span[i]), hi[i] + (0 if periodic[i] else span[i]), nq)
                    for i in range(d)])
     qdt = np.float32 if rng.random() < 0.5 else np.float64
+    if rng.random() < 0.3:
+        # the quantised mode; periodic axes get an odd node count, so that no
+        # pair of nodes is exactly half a period apart (where the minimum
+        # image is not unique)
+        gn = tuple(n | 1 if periodic[i] else n for i, n in enumerate(grid_n))
+        spec = dataclasses.replace(spec, quantize=1, grid_n=gn)
     return spec, W.Hills(cen, hts), q.astype(qdt)
 
 
@@ -71,8 +77,9 @@ def test_random_spec_parity(seed):
         # terms below the FP32 range: flushed in FP32 arithmetic or FP32 outputs
         fl = fp32_floor(hills.heights) if hills.n and (out32 or not fp64) else 0.0
         gfl = fl * 1e4 * max(1.0, max(1.0 / w ** 2 for w in spec.width))
+        snap = (lambda i, x: oracle.snap(spec, i, x)) if spec.quantize else None
         E0, E = rounding_error_scales(spec, hills.centers, hills.heights, qq, 2.0 ** -53 if fp64 else 2.0 ** -24,
-                                      2.0 ** -53 if fp64 else 2.0 ** -24)
+                                      2.0 ** -53 if fp64 else 2.0 ** -24, snap=snap)
         got_V, got_dV = host(V), host(dV)
         check_bound(f"seed {seed} prec {prec} V", got_V, Vo, sV, tol, fl + slope * E0)
         check_bound(f"seed {seed} prec {prec} dV", got_dV, dVo, sG, tol, gfl + slope[None, :] * E)
