@@ -173,3 +173,47 @@ def test_serving_rejects_bad_input(lib):
     srv.close()
     small.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("kinds", [(W.CV_TORSION,), (W.CV_COM_DIST, W.CV_TORSION, W.CV_RMSD_OFF)])
+def test_serving_one_and_three_cvs(lib, kinds):
+    """The serving loop in 1-D and 3-D CV spaces (walkers of uneven size with
+    a torsion; a COM distance, a torsion and an offset RMSD), with evictions
+    and deposits: every request against the oracle."""
+    import torch
+    from tests.test_gpu_force_random import _walkers
+    rng = np.random.default_rng(77 + len(kinds))
+    wk = _walkers(rng, kinds, 20)
+    D = len(kinds)
+    periodic = tuple(1 if k == W.CV_TORSION else 0 for k in kinds)
+    lo = tuple(-np.pi if k == W.CV_TORSION else 0.0 for k in kinds)
+    hi = tuple(np.pi if k == W.CV_TORSION else (3.5 if k == W.CV_COM_DIST else 1.0) for k in kinds)
+    width = tuple(0.4 if k == W.CV_TORSION else (0.15 if k == W.CV_COM_DIST else 0.05) for k in kinds)
+    spec = W.BiasSpec(ndim=D, periodic=periodic, lo=lo, hi=hi, width=width, grid_n=(0, 0, 0))
+    nh = 1500
+    cen = np.vstack([rng.uniform(lo[i], hi[i], nh) for i in range(D)])
+    hts = rng.uniform(0.1, 1.2, nh)
+    ctx = lib.Context(spec, nh + 1024)
+    lib.bias_deposit(ctx, torch.tensor(cen, device="cuda"), torch.tensor(hts, device="cuda"))
+    torch.cuda.synchronize()
+    budget = 28 * int(wk.n_atoms.astype(np.int64).sum() // 3)
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=8, streams=2, deposit_every=4,
+                     height0=1.0, height_decay=10000.0, amplitude=AMP)
+    _register(srv, wk)
+    t, w, step = W.serving_requests(seed=4, n_walkers=wk.nw, rate=50_000.0, n_requests=240)
+    out = srv.replay(w, step, t)
+    assert out["stats"]["completed"] == len(t) and out["stats"]["evictions"] > 0
+    centers, heights = lib.abp_hills_export(ctx)
+    assert np.array_equal(centers[:, :nh], cen)
+    for r in range(len(t)):
+        s_o, V_o, dV_o, A0, A = _oracle_request(spec, centers, heights, wk, int(w[r]), int(step[r]),
+                                                int(out["version"][r]))
+        ds = out["s"][:, r] - s_o
+        for a in range(D):
+            if periodic[a]:
+                ds[a] = _wrap(ds[a])
+        assert np.abs(ds).max() < 1e-12, (r, ds)
+        check_bound("served V", np.array([out["V"][r]]), np.array([V_o]), np.array([A0]))
+        check_bound("served dVds", out["dVds"][:, r], dV_o, A)
+    srv.close()
+    ctx.close()
