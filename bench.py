@@ -334,12 +334,22 @@ def grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV):
     abp.abp_sync(gctx)
     extra["grid_build_ms"] = times[1]
     extra["grid_build_first_call_ms"] = times[0]
+    # algorithmic work of the deposit: 2^ndim FMAs per (node, hill)
+    nodes = 1
+    for n in spec.grid_n[:spec.ndim]:
+        nodes *= n
+    dep_tflops = 2.0 * (1 << spec.ndim) * nodes * nh / (times[1] * 1e-3) / 1e12
+    extra["grid_build_roofline"] = {"bound": "mfma", "achieved": dep_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": dep_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                                    "note": "FP64 MFMA deposit; the timed call includes the history append "
+                                            "and the split reduction"}
 
     def grid_step():
         abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
     el3, _ = timed(grid_step, args.steps, 2, stream)
     extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
-                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9}
+                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9,
+                          "frac_hbm_compulsory": nq * 20 * args.steps / el3 / 1e9 / HBM_PEAK_GBS}
     log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
     gctx.close()
     return extra
@@ -369,7 +379,8 @@ def stress_grid_leg(abp, W, torch):
     flops = 2.0 * 8 * 128 ** 3 * hills.n
     log(f"bench: stress grid build {times[1]:.1f} ms ({flops / times[1] / 1e9:.1f} TFLOP/s of deposit FMAs)")
     return {"hills": hills.n, "grid": "128^3 x 8 FP64", "build_ms": times[1], "first_call_ms": times[0],
-            "deposit_tflops": flops / times[1] / 1e9}
+            "deposit_tflops": flops / times[1] / 1e9,
+            "frac_fp64_peak": flops / times[1] / 1e9 / FP64_VECTOR_PEAK_TFLOPS}
 
 
 def main():
@@ -490,6 +501,12 @@ def main():
             abp.bias_eval(ctx, qd, prec=prec, V=V, dVds=dV)
         el2, _ = timed(fn, steps, 1, stream)
         extra[name] = {"walker_steps_per_s": nq * steps / el2, "ms_per_step": el2 / steps * 1e3}
+        if prec == abp.ABP_PREC_FP64:
+            # the same 18 algorithmic flops per pair, against the FP64 peak
+            tf = nq * steps / el2 * nh * FLOPS_PER_PAIR_2D / 1e12
+            extra[name]["roofline"] = {"bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_PEAK_TFLOPS,
+                                       "note": "the exponential (about 16 FP64 instructions) is not counted"}
         log(f"bench: {name} {nq * steps / el2:.4e} walker-steps/s")
     extra.update(grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV))
     del build_s
