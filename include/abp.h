@@ -189,7 +189,9 @@ abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* ce
  * Outputs V[nq] and dVds[ndim][nq] have the same dtype as q.
  * prec selects the hill-sum arithmetic; the grid path always uses FP64.
  * The result for a query depends only on that query and the hills, not on nq
- * or its position in the batch. nq = 0 is a no-op. */
+ * or its position in the batch. A query with a non-finite coordinate gets NaN
+ * in V and all of its dVds entries (every mode and precision; it is not an
+ * error and is not counted as clamped). nq = 0 is a no-op. */
 abp_status bias_eval(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, int64_t nq, abp_dtype dtype,
                      const void* q, int64_t n_visible, void* V, void* dVds, abp_stream stream);
 

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(const DirectArgs A) {
   for (int i = 0; i < D; ++i) {
     const double x = load_q(A, i, iq);
     finite = finite && isfinite(x);
-    tq[i] = work64(A.K, i, eval_coord(A.K, i, x));
+    tq[i] = work64(A.K, i, eval_coord(A.K, i, isfinite(x) ? x : A.K.lo[i]));
   }
 #pragma unroll
   for (int r = 0; r <= D; ++r) P[r] = 0.0;
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_f64(const DirectArgs A) {
 #pragma unroll
   for (int i = 0; i < D; ++i) dh[i] = P[i + 1] * A.K.gs64[i];
   apply_transform<D>(A.K, P[0], dh, V, dV);
-  if (!finite) {                       // the terms clamp their exponents; say so here
+  if (!finite) {                       // a non-finite query coordinate gives NaN outputs
     V = __builtin_nan("");
 #pragma unroll
     for (int i = 0; i < D; ++i) dV[i] = V;

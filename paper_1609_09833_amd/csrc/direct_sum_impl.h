@@ -64,12 +64,18 @@ __global__ __launch_bounds__(kBlock) void k_direct_f32(const DirectArgs A) {
 #pragma unroll
   for (int i = 0; i < D; ++i) { kf[i] = A.K.kf32[i]; ua[i] = A.K.ua32[i]; }
   const float pl = A.K.pl32;
+  bool finite[Q];                     // a non-finite query coordinate gives NaN outputs
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     int64_t iq = first + j;
     iq = iq < A.nq ? iq : A.nq - 1;
+    finite[j] = true;
 #pragma unroll
-    for (int i = 0; i < D; ++i) qw[j][i] = work32(A.K, i, eval_coord(A.K, i, load_q(A, i, iq)));
+    for (int i = 0; i < D; ++i) {
+      const double x = load_q(A, i, iq);
+      finite[j] = finite[j] && isfinite(x);
+      qw[j][i] = work32(A.K, i, eval_coord(A.K, i, isfinite(x) ? x : A.K.lo[i]));
+    }
 #pragma unroll
     for (int r = 0; r <= D; ++r) { S[j][r] = 0.0f; Cc[j][r] = 0.0f; P[j][r] = 0.0f; }
   }
@@ -128,6 +134,11 @@ __global__ __launch_bounds__(kBlock) void k_direct_f32(const DirectArgs A) {
     }
     double V, dV[D];
     apply_transform<D>(A.K, h, dh, V, dV);
+    if (!finite[j]) {
+      V = __builtin_nan("");
+#pragma unroll
+      for (int i = 0; i < D; ++i) dV[i] = V;
+    }
     const int64_t iq = first + j;
     if (iq < A.nq) store_out<D>(A, iq, V, dV);
   }

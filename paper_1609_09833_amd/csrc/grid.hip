@@ -498,11 +498,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_eval(const EvalArgs A) {
     int64_t j = base + (int64_t)u * kBlock;
     j = j < A.nq ? j : A.nq - 1;
     double s[D];
+    bool finite = true;
 #pragma unroll
-    for (int i = 0; i < D; ++i)
+    for (int i = 0; i < D; ++i) {
       s[i] = A.q_f64 ? static_cast<const double*>(A.q)[i * A.nq + j]
                      : (double)static_cast<const float*>(A.q)[i * A.nq + j];
+      finite = finite && isfinite(s[i]);
+    }
     hermite_eval<D>(A.K, A.grid, s, h[u], dh[u], clamped[u]);
+    if (!finite) {                     // a non-finite query coordinate gives NaN outputs
+      clamped[u] = false;
+      h[u] = __builtin_nan("");
+#pragma unroll
+      for (int i = 0; i < D; ++i) dh[u][i] = h[u];
+    }
   }
 #pragma unroll
   for (int u = 0; u < kEvalQ; ++u) {

@@ -153,3 +153,28 @@ def test_empty_inputs_and_empty_history(lib, small):
     with pytest.raises(lib.AbpError) as err:
         lib.bias_eval(nogrid, torch.zeros((2, 4), dtype=torch.float64, device="cuda"), mode=lib.ABP_EVAL_GRID)
     assert err.value.status == lib.ABP_E_INVAL
+
+
+@pytest.mark.parametrize("mode,prec", [("direct", 0), ("direct", 1), ("direct", 2), ("grid", 0)])
+@pytest.mark.parametrize("q_f64", [False, True])
+def test_non_finite_queries_give_nan_rows(lib, small, mode, prec, q_f64):
+    """NaN and +-inf query coordinates give NaN outputs for those queries
+    only; every other query's result is bitwise that of a clean batch."""
+    import torch
+    wk, spec, hills = small
+    ctx = _ctx(lib, spec, hills)
+    rng = np.random.default_rng(8)
+    q = np.vstack([rng.uniform(0.0, 1.5, 700), rng.uniform(-np.pi, np.pi, 700)])
+    q = q.astype(np.float64 if q_f64 else np.float32)
+    bad = q.copy()
+    rows = [3, 4, 5, 600, 699]
+    bad[0, 3], bad[1, 4], bad[0, 5], bad[1, 600], bad[0, 699] = np.nan, np.inf, -np.inf, np.nan, np.inf
+    m = lib.ABP_EVAL_GRID if mode == "grid" else lib.ABP_EVAL_DIRECT
+    V0, dV0 = lib.bias_eval(ctx, to_dev(q), mode=m, prec=prec)
+    V1, dV1 = lib.bias_eval(ctx, to_dev(bad), mode=m, prec=prec)
+    lib.abp_sync(ctx)                                   # not an error
+    V0, dV0, V1, dV1 = host(V0), host(dV0), host(V1), host(dV1)
+    assert np.all(np.isnan(V1[rows])) and np.all(np.isnan(dV1[:, rows]))
+    keep = np.setdiff1d(np.arange(q.shape[1]), rows)
+    assert np.array_equal(V1[keep], V0[keep]) and np.array_equal(dV1[:, keep], dV0[:, keep])
+    assert np.all(np.isfinite(V1[keep]))
