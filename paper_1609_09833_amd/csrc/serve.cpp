@@ -10,8 +10,9 @@
 //      evicting least recently used idle walkers when the budget is short,
 //   4. if a stream is free, forms a batch from the walkers that are resident,
 //      idle and have a request, and enqueues: descriptor upload, the engine
-//      step (positions for this step; masses/forces for newly admitted
-//      walkers), the bias-force stages, the output download, an event.
+//      step (CV-atom positions for this step, cleared CV-atom forces, and
+//      CV-atom masses for newly admitted walkers), the bias-force stages, the
+//      output download, an event.
 // Requests in one batch see the same history version (hills committed when
 // the batch was formed); deposits go to slots reserved in formation order.
 #include <hip/hip_runtime.h>

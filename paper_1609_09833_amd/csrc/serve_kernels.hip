@@ -1,10 +1,11 @@
 // Device side of the serving loop: the synthetic engine step that prepares
 // each batched walker before its bias-force evaluation.
 //
-// For every request of a batch: if its walker was just admitted, copy the
-// walker's masses from mapped host memory into the device pool and zero its
-// force arrays; then write the positions of its CV atoms for this step and
-// clear their forces (the bias force is added to them afterwards),
+// For every request of a batch: write the positions of its walker's CV atoms
+// for this step and clear their forces (the bias force is added to them
+// afterwards), and if the walker was just admitted copy the CV atoms' masses
+// from mapped host memory into the device pool (the bias path reads no other
+// atom, so only CV atoms cross PCIe),
 //   x = x0 + amplitude * u(walker, step, atom, coordinate),
 // where x0 is read from mapped host memory and u in [-1, 1) comes from an
 // integer hash (the "lowbias32" mixer, C. Wellons, 2018). The arithmetic uses
@@ -38,27 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
   const int64_t base = E.atom_base[j];
   const int32_t n = E.n_atoms[j];
   const int64_t hbase = E.host_base[j];
-  if (E.fresh[j]) {
-    // PCIe reads are issued kInFlight at a time before any is used.
-    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)kBlock * kInFlight) {
-      float m[kInFlight];
-#pragma unroll
-      for (int u = 0; u < kInFlight; ++u) {
-        const int64_t i = i0 + (int64_t)u * kBlock + tid;
-        m[u] = i < n ? E.h_mass[hbase + i] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < kInFlight; ++u) {
-        const int64_t i = i0 + (int64_t)u * kBlock + tid;
-        if (i < n) {
-          E.mass[base + i] = m[u];
-          E.fx[base + i] = 0.0f;
-          E.fy[base + i] = 0.0f;
-          E.fz[base + i] = 0.0f;
-        }
-      }
-    }
-  }
+  const bool fresh = E.fresh[j] != 0;
   const uint32_t w = (uint32_t)E.walker[j];
   const uint32_t st = (uint32_t)E.step[j];
   // CV atoms of all lists, flattened: entry r of list q sits at r - start[q].
@@ -79,19 +60,21 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
         atom[u] = (i >= 0 && i < n) ? i : -1;        // the bias kernels flag a bad index
       }
     }
-    float px[kInFlight], py[kInFlight], pz[kInFlight];
+    float px[kInFlight], py[kInFlight], pz[kInFlight], pm[kInFlight];
 #pragma unroll
     for (int u = 0; u < kInFlight; ++u) {
       const int64_t hg = hbase + (atom[u] < 0 ? 0 : atom[u]);   // atom 0 stands in: always valid
       px[u] = E.h_x0[hg];
       py[u] = E.h_y0[hg];
       pz[u] = E.h_z0[hg];
+      pm[u] = fresh ? E.h_mass[hg] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < kInFlight; ++u) {
       if (atom[u] < 0) continue;
       const int64_t g = base + atom[u];
       const uint32_t a = (uint32_t)atom[u];
+      if (fresh) E.mass[g] = pm[u];
       E.x[g] = __fadd_rn(px[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 0u)));
       E.y[g] = __fadd_rn(py[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 1u)));
       E.z[g] = __fadd_rn(pz[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 2u)));
