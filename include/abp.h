@@ -259,8 +259,11 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  * that share the context's hill history. Not in the paper (one walker per MD
  * engine there); it serves the same per-step problem to many engines at once.
  *
- * Each walker's engine state (positions, masses and forces of all its atoms,
- * 28 bytes per atom) lives in device memory while the walker is admitted.
+ * Each walker's engine state (base and current positions, masses and forces
+ * of all its atoms, ABP_SERVER_BYTES_PER_ATOM bytes per atom) lives in device
+ * memory while the walker is admitted; admission copies the base positions
+ * and masses of the walker's CV atoms from host memory, the only atoms the
+ * bias path reads.
  * Walkers are admitted first come first served against an HBM budget; when
  * memory is short the least recently used idle walker is evicted. A request
  * (walker, step) is evaluated against the hills committed when its batch is
@@ -274,8 +277,10 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  * (walker, step, atom, coordinate). The bias path itself is bias_force's. */
 typedef struct abp_server abp_server;
 
+#define ABP_SERVER_BYTES_PER_ATOM 40  /* ten FP32 arrays: x0, y0, z0, x, y, z, mass, fx, fy, fz */
+
 typedef struct {
-  int64_t hbm_budget_bytes;  /* device memory for walker engine state (28 bytes per atom) */
+  int64_t hbm_budget_bytes;  /* device memory for walker engine state (ABP_SERVER_BYTES_PER_ATOM per atom) */
   int32_t max_batch;         /* requests per batch, >= 1 (1 = one launch per request) */
   int32_t streams;           /* batches in flight, 1..8 */
   int32_t deposit_every;     /* deposit period in steps; 0: never */

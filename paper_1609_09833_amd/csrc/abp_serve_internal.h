@@ -10,14 +10,15 @@ struct EngineArgs {
   const int64_t* atom_base;    // [nb] device offset of the walker's atoms in the pools
   const int32_t* n_atoms;      // [nb]
   const int64_t* host_base;    // [nb] offset of the walker's atoms in the host arrays
-  const int32_t* fresh;        // [nb] 1: walker admitted for this batch (initialise masses, forces)
+  const int32_t* fresh;        // [nb] 1: walker admitted for this batch (copy base positions, masses)
   const int32_t* walker;       // [nb] walker id (hash input)
   const int64_t* step;         // [nb] MD step (hash input)
   int32_t nlists;              // 2 * ncv
   const int32_t* list_beg;     // [nlists][nb] into list_idx
   const int32_t* list_len;     // [nlists][nb]
   const int32_t* list_idx;     // device list pool
-  const float* h_x0;           // mapped pinned host: base positions and masses of every walker
+  const float* h_x0;           // mapped pinned host: base positions and masses of every walker,
+                               // read only for a walker just admitted
   const float* h_y0;
   const float* h_z0;
   const float* h_mass;
@@ -29,6 +30,9 @@ struct EngineArgs {
   float* fx;
   float* fy;
   float* fz;
+  float* x0;                   // device pools: base positions of resident walkers' CV atoms
+  float* y0;
+  float* z0;
 };
 
 hipError_t launch_engine_step(const EngineArgs& E, hipStream_t stream);

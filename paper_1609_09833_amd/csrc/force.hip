@@ -895,6 +895,8 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
 // sums t, t + 128, ... in order, then the block tree; transform, outputs,
 // deposit, chain rule.
 // ---------------------------------------------------------------------------
+constexpr int kMergeBatch = 8;
+
 template <int D, bool FP64>
 __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
   constexpr int N = D + 1;
@@ -910,27 +912,8 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
   const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
 #pragma unroll
   for (int r = 0; r < N; ++r) { hi[r] = 0.0f; lo[r] = 0.0f; v64[r] = 0.0; }
-  for (int64_t c = tid; c < nch; c += kFBlock) {
-    const int64_t at = (w * F.pmax + c) * N;
-    float ph[N], pl[N];
-    double pv[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      if (FP64) {
-        pv[r] = F.part64[at + r];
-        ph[r] = 0.0f;
-        pl[r] = 0.0f;
-      } else {
-        const float2 q = F.part32[at + r];
-        ph[r] = q.x;
-        pl[r] = q.y;
-        pv[r] = 0.0;
-      }
-    }
-    merge_part<N, FP64>(hi, lo, v64, ph, pl, pv, comp);
-  }
-  if (FP64) block_sum<N, kFBlock>(v64, red);
-  else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
+  // the CV state (to LDS, published by the merge's barriers) and the cached
+  // entries are fetched first, so their loads overlap those of the chunk sums
   {
     const int* src = reinterpret_cast<const int*>(F.state + w);
     int* dst = reinterpret_cast<int*>(&S);
@@ -947,6 +930,35 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
     ent[k].m = 0.0f;
     if (k * kFBlock + tid < total) ent[k] = in[k * kFBlock + tid];
   }
+  // kMergeBatch of a thread's chunk sums are loaded before any is merged (the
+  // loads overlap; the merge order is unchanged)
+  for (int64_t c0 = tid; c0 < nch; c0 += kMergeBatch * kFBlock) {
+    float ph[kMergeBatch][N], pl[kMergeBatch][N];
+    double pv[kMergeBatch][N];
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u) {
+      const int64_t c = c0 + (int64_t)u * kFBlock;
+      const int64_t at = (w * F.pmax + (c < nch ? c : c0)) * N;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        if (FP64) {
+          pv[u][r] = F.part64[at + r];
+          ph[u][r] = 0.0f;
+          pl[u][r] = 0.0f;
+        } else {
+          const float2 q = F.part32[at + r];
+          ph[u][r] = q.x;
+          pl[u][r] = q.y;
+          pv[u][r] = 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u)
+      if (c0 + (int64_t)u * kFBlock < nch) merge_part<N, FP64>(hi, lo, v64, ph[u], pl[u], pv[u], comp);
+  }
+  if (FP64) block_sum<N, kFBlock>(v64, red);
+  else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
   finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
 }
 

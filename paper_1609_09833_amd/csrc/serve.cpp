@@ -40,7 +40,7 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
   } while (0)
 
 constexpr int kMaxLists = 6;
-constexpr int64_t kBytesPerAtom = 28;      // x, y, z, mass, fx, fy, fz (FP32)
+constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;   // ten FP32 pool arrays
 
 struct Walker {
   int32_t n = 0;
@@ -322,7 +322,7 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     return sfail(ABP_E_DEVICE, "cannot select the context's device");
   }
   S->pool_atoms = desc->hbm_budget_bytes / kBytesPerAtom;
-  if (hipMalloc(&S->d_pool, sizeof(float) * 7 * S->pool_atoms) != hipSuccess) {
+  if (hipMalloc(&S->d_pool, sizeof(float) * 10 * S->pool_atoms) != hipSuccess) {
     delete S;
     return sfail(ABP_E_NOMEM, "cannot allocate the walker pool");
   }
@@ -632,6 +632,9 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
     E.fx = pool_array(S, 4);
     E.fy = pool_array(S, 5);
     E.fz = pool_array(S, 6);
+    E.x0 = pool_array(S, 7);
+    E.y0 = pool_array(S, 8);
+    E.z0 = pool_array(S, 9);
     SRV_TRY(abp::launch_engine_step(E, sl.stream));
     abp::ForceArgs A;
     std::memset(&A, 0, sizeof(A));

@@ -3,14 +3,16 @@
 //
 // For every request of a batch: write the positions of its walker's CV atoms
 // for this step and clear their forces (the bias force is added to them
-// afterwards), and if the walker was just admitted copy the CV atoms' masses
-// from mapped host memory into the device pool (the bias path reads no other
-// atom, so only CV atoms cross PCIe),
+// afterwards),
 //   x = x0 + amplitude * u(walker, step, atom, coordinate),
-// where x0 is read from mapped host memory and u in [-1, 1) comes from an
-// integer hash (the "lowbias32" mixer, C. Wellons, 2018). The arithmetic uses
-// explicitly rounded float operations so a host can reproduce the positions
-// bit for bit. This stands in for an MD engine; it is not part of the method.
+// where u in [-1, 1) comes from an integer hash (the "lowbias32" mixer,
+// C. Wellons, 2018). The base positions x0 are the walker's resident state:
+// when the walker was just admitted they and the masses are copied from
+// mapped host memory into the device pool, and afterwards read from there (the
+// bias path reads no atom but the CV atoms, so only those cross PCIe, once
+// per admission). The arithmetic uses explicitly rounded float operations so
+// a host can reproduce the positions bit for bit. This stands in for an MD
+// engine; it is not part of the method.
 #include "abp_serve_internal.h"
 
 namespace abp {
@@ -31,7 +33,7 @@ __device__ __forceinline__ float unit_hash(uint32_t w, uint32_t step, uint32_t a
   return (float)(int32_t)((h >> 16) & 0xffffu) * (1.0f / 32768.0f) - 1.0f;
 }
 
-constexpr int kInFlight = 16;   // mapped-memory loads each thread keeps in flight
+constexpr int kInFlight = 16;   // loads each thread keeps in flight (PCIe latency on admission)
 
 __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
   const int j = blockIdx.x;
@@ -61,20 +63,36 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
       }
     }
     float px[kInFlight], py[kInFlight], pz[kInFlight], pm[kInFlight];
+    if (fresh) {                                    // uniform per block
 #pragma unroll
-    for (int u = 0; u < kInFlight; ++u) {
-      const int64_t hg = hbase + (atom[u] < 0 ? 0 : atom[u]);   // atom 0 stands in: always valid
-      px[u] = E.h_x0[hg];
-      py[u] = E.h_y0[hg];
-      pz[u] = E.h_z0[hg];
-      pm[u] = fresh ? E.h_mass[hg] : 0.0f;
+      for (int u = 0; u < kInFlight; ++u) {
+        const int64_t hg = hbase + (atom[u] < 0 ? 0 : atom[u]);   // atom 0 stands in: always valid
+        px[u] = E.h_x0[hg];
+        py[u] = E.h_y0[hg];
+        pz[u] = E.h_z0[hg];
+        pm[u] = E.h_mass[hg];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kInFlight; ++u) {
+        const int64_t g = base + (atom[u] < 0 ? 0 : atom[u]);
+        px[u] = E.x0[g];
+        py[u] = E.y0[g];
+        pz[u] = E.z0[g];
+        pm[u] = 0.0f;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kInFlight; ++u) {
       if (atom[u] < 0) continue;
       const int64_t g = base + atom[u];
       const uint32_t a = (uint32_t)atom[u];
-      if (fresh) E.mass[g] = pm[u];
+      if (fresh) {
+        E.x0[g] = px[u];
+        E.y0[g] = py[u];
+        E.z0[g] = pz[u];
+        E.mass[g] = pm[u];
+      }
       E.x[g] = __fadd_rn(px[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 0u)));
       E.y[g] = __fadd_rn(py[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 1u)));
       E.z[g] = __fadd_rn(pz[u], __fmul_rn(E.amplitude, unit_hash(w, st, a, 2u)));

@@ -59,6 +59,7 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(abp_server_desc), offsetof(abp_server_desc, amplitude),
          offsetof(abp_server_desc, cv_kind));
   printf("%zu %zu\\n", sizeof(abp_server_stats), offsetof(abp_server_stats, wall_seconds));
+  printf("%d\\n", ABP_SERVER_BYTES_PER_ATOM);
   return 0;
 }
 """)
@@ -74,6 +75,7 @@ int main(void) {
     assert vals[2] == [C.sizeof(abp.WalkersDesc), abp.WalkersDesc.x.offset, abp.WalkersDesc.fz.offset]
     assert vals[3] == [C.sizeof(abp.ServerDesc), abp.ServerDesc.amplitude.offset, abp.ServerDesc.cv_kind.offset]
     assert vals[4] == [C.sizeof(abp.ServerStats), abp.ServerStats.wall_seconds.offset]
+    assert vals[5] == [abp.ABP_SERVER_BYTES_PER_ATOM]
 
 
 def test_host_side_validation_without_gpu(lib):

@@ -72,7 +72,8 @@ def _wrap(d):
 def test_serving_with_deposits_matches_oracle(lib):
     """Batched, evicting, depositing replay: every request checked against the oracle."""
     spec, hills, wk, ctx = _setup(lib)
-    budget = 28 * int(wk.n_atoms.astype(np.int64).sum() // 3)     # about a third of the walkers fit
+    # about a third of the walkers fit
+    budget = lib.ABP_SERVER_BYTES_PER_ATOM * int(wk.n_atoms.astype(np.int64).sum() // 3)
     srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=16, streams=2, deposit_every=3,
                      height0=1.2, height_decay=20000.0, amplitude=AMP)
     _register(srv, wk)
@@ -150,7 +151,7 @@ def test_serving_rejects_bad_input(lib):
         lib.Server(ctx, [W.CV_TORSION, W.CV_TORSION])         # torsion on a non-periodic axis
     with pytest.raises(lib.AbpError):
         lib.Server(ctx, wk.kinds, max_batch=0)
-    small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=28 * 1000)
+    small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=lib.ABP_SERVER_BYTES_PER_ATOM * 1000)
     b, n = int(wk.atom_base[0]), int(wk.n_atoms[0])
     lens, idx, rx, ry, rz = W.walker_lists(wk, 0)
     with pytest.raises(lib.AbpError) as e:
@@ -196,7 +197,7 @@ def test_serving_one_and_three_cvs(lib, kinds):
     ctx = lib.Context(spec, nh + 1024)
     lib.bias_deposit(ctx, torch.tensor(cen, device="cuda"), torch.tensor(hts, device="cuda"))
     torch.cuda.synchronize()
-    budget = 28 * int(wk.n_atoms.astype(np.int64).sum() // 3)
+    budget = lib.ABP_SERVER_BYTES_PER_ATOM * int(wk.n_atoms.astype(np.int64).sum() // 3)
     srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=8, streams=2, deposit_every=4,
                      height0=1.0, height_decay=10000.0, amplitude=AMP)
     _register(srv, wk)
