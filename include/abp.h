@@ -311,8 +311,9 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
 /* Wait for outstanding work and free the server (not the context). */
 abp_status abp_server_destroy(abp_server* srv);
 
-/* Register a walker (HOST arrays, copied): n_atoms base positions x0/y0/z0
- * and masses; list_len[2*ncv] lengths of the CV lists (CV a, slot t at
+/* Register a walker (HOST arrays): n_atoms base positions x0/y0/z0 and
+ * masses, of which the server keeps a copy for the CV atoms (the only atoms
+ * it touches); list_len[2*ncv] lengths of the CV lists (CV a, slot t at
  * 2a+t, rules as in abp_cv_desc) and list_idx their concatenation in that
  * order; ref_x/y/z aligned with list_idx (NULL when no CV is RMSD_OFF).
  * Lists are checked here (ABP_E_INVAL); a walker whose state exceeds the

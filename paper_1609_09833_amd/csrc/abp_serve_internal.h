@@ -9,19 +9,14 @@ struct EngineArgs {
   int64_t nb;                  // requests in the batch
   const int64_t* atom_base;    // [nb] device offset of the walker's atoms in the pools
   const int32_t* n_atoms;      // [nb]
-  const int64_t* host_base;    // [nb] offset of the walker's atoms in the host arrays
-  const int32_t* fresh;        // [nb] 1: walker admitted for this batch (copy base positions, masses)
+  const int64_t* stage_off;    // [nb] first staged entry of a walker admitted for this batch, else -1
+  const float4* stage;         // staged (x0, y0, z0, mass) of those walkers' CV entries, in list order
   const int32_t* walker;       // [nb] walker id (hash input)
   const int64_t* step;         // [nb] MD step (hash input)
   int32_t nlists;              // 2 * ncv
   const int32_t* list_beg;     // [nlists][nb] into list_idx
   const int32_t* list_len;     // [nlists][nb]
   const int32_t* list_idx;     // device list pool
-  const float* h_x0;           // mapped pinned host: base positions and masses of every walker,
-                               // read only for a walker just admitted
-  const float* h_y0;
-  const float* h_z0;
-  const float* h_mass;
   float amplitude;             // nm; positions move by at most this much from x0
   float* x;                    // device pools
   float* y;

@@ -895,7 +895,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
 // sums t, t + 128, ... in order, then the block tree; transform, outputs,
 // deposit, chain rule.
 // ---------------------------------------------------------------------------
-constexpr int kMergeBatch = 8;
+constexpr int kMergeBatch = 16;
 
 template <int D, bool FP64>
 __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {

@@ -9,10 +9,11 @@
 //   3. admits waiting walkers first come first served into the device pools,
 //      evicting least recently used idle walkers when the budget is short,
 //   4. if a stream is free, forms a batch from the walkers that are resident,
-//      idle and have a request, and enqueues: descriptor upload, the engine
-//      step (CV-atom positions for this step, cleared CV-atom forces, and
-//      CV-atom masses for newly admitted walkers), the bias-force stages, the
-//      output download, an event.
+//      idle and have a request, and enqueues: descriptor upload (with the
+//      base positions and masses of the CV atoms of walkers admitted since
+//      their last batch, gathered here), the engine step (those stored into
+//      the pool, CV-atom positions for this step, cleared CV-atom forces), the
+//      bias-force stages, the output download, an event.
 // Requests in one batch see the same history version (hills committed when
 // the batch was formed); deposits go to slots reserved in formation order.
 #include <hip/hip_runtime.h>
@@ -21,9 +22,11 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <list>
 #include <map>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -41,10 +44,12 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
 
 constexpr int kMaxLists = 6;
 constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;   // ten FP32 pool arrays
+constexpr size_t kStageBytes0 = (size_t)1 << 20;   // initial staging area per stream (grows on demand)
 
 struct Walker {
   int32_t n = 0;
-  int64_t host_base = 0;     // offset in the host base-position / mass arrays
+  int64_t img_base = 0;      // first entry of the walker's CV image
+  int64_t entries = 0;       // CV-list entries, all lists
   int64_t list_base = 0;     // offset in the list pool
   int32_t len[kMaxLists] = {0, 0, 0, 0, 0, 0};
   int64_t atom_base = -1;    // device pool offset when resident
@@ -65,27 +70,29 @@ struct Slot {
   int64_t version = 0;
   std::vector<int64_t> reqs;
   std::vector<int64_t> dep_slots;   // history slot per request or -1
-  char* h_desc = nullptr;            // pinned descriptor
+  char* h_desc = nullptr;            // pinned descriptor, then the staged base positions
   char* d_desc = nullptr;
+  size_t desc_cap = 0;               // bytes of h_desc and of d_desc
   double* h_out = nullptr;           // pinned outputs: s[ncv][nb], V[nb], dV[ncv][nb]
   double* d_out = nullptr;
   void* d_ws = nullptr;              // bias_force workspace
   size_t ws_bytes = 0;
 };
 
-// Byte layout of a batch descriptor with nb requests (arrays packed at stride nb).
+// Byte layout of a batch descriptor with nb requests (arrays packed at stride
+// nb). The staging area follows at `total`: (x0, y0, z0, mass) of the CV
+// entries of every walker admitted for this batch, in list order.
 struct DescLayout {
-  size_t atom_base, host_base, step, dep_slot, dep_height, n_atoms, fresh, walker, list_beg, list_len, total;
+  size_t atom_base, stage_off, step, dep_slot, dep_height, n_atoms, walker, list_beg, list_len, total;
   static size_t up(size_t x) { return (x + 15) / 16 * 16; }
   DescLayout(int64_t nb, int nlists) {
     size_t o = 0;
     atom_base = o; o = up(o + 8 * nb);
-    host_base = o; o = up(o + 8 * nb);
+    stage_off = o; o = up(o + 8 * nb);
     step = o; o = up(o + 8 * nb);
     dep_slot = o; o = up(o + 8 * nb);
     dep_height = o; o = up(o + 8 * nb);
     n_atoms = o; o = up(o + 4 * nb);
-    fresh = o; o = up(o + 4 * nb);
     walker = o; o = up(o + 4 * nb);
     list_beg = o; o = up(o + 4 * nb * nlists);
     list_len = o; o = up(o + 4 * nb * nlists);
@@ -108,20 +115,22 @@ struct abp_server {
   int kind[3] = {0, 0, 0};
   // registered walkers (host copies until the first replay)
   std::vector<Walker> walkers;
-  std::vector<float> hx0, hy0, hz0, hm;
+  // CV images: (x0, y0, z0, mass) of every walker's CV-list entries, in list
+  // order (the only atoms the engine step and the bias path touch)
+  std::vector<float4> himg;
   std::vector<int32_t> lidx;
   std::vector<float> lrx, lry, lrz;
   bool dirty = true;
-  // mapped pinned host copies of base positions and masses
-  float* p_x0 = nullptr; float* p_y0 = nullptr; float* p_z0 = nullptr; float* p_m = nullptr;
-  float* m_x0 = nullptr; float* m_y0 = nullptr; float* m_z0 = nullptr; float* m_m = nullptr;   // device views
   // device list pool
   int32_t* d_lidx = nullptr;
   float* d_rx = nullptr; float* d_ry = nullptr; float* d_rz = nullptr;
   // device atom pools
   int64_t pool_atoms = 0;
-  float* d_pool = nullptr;           // 7 arrays of pool_atoms floats
-  std::map<int64_t, int64_t> free_ranges;   // offset -> length
+  float* d_pool = nullptr;           // 10 arrays of pool_atoms floats
+  // free atom ranges of the pools, by offset (for merging) and by length
+  // (best fit in O(log n): admissions are frequent and the pools fragment)
+  std::map<int64_t, int64_t> free_ranges;            // offset -> length
+  std::set<std::pair<int64_t, int64_t>> free_by_len; // (length, offset)
   std::list<int32_t> lru;            // idle resident walkers, least recent first
   std::deque<int32_t> admission;     // walkers waiting for memory
   std::deque<int32_t> ready;         // resident, idle, with a request
@@ -137,50 +146,48 @@ namespace {
 
 float* pool_array(abp_server* S, int which) { return S->d_pool + (int64_t)which * S->pool_atoms; }
 
+void range_insert(abp_server* S, int64_t off, int64_t n) {
+  S->free_ranges.emplace(off, n);
+  S->free_by_len.emplace(n, off);
+}
+
+void range_erase(abp_server* S, std::map<int64_t, int64_t>::iterator it) {
+  S->free_by_len.erase({it->second, it->first});
+  S->free_ranges.erase(it);
+}
+
+// Best fit: the shortest free range that holds n atoms (lowest offset among equals).
 bool pool_alloc(abp_server* S, int64_t n, int64_t* off) {
-  for (auto it = S->free_ranges.begin(); it != S->free_ranges.end(); ++it) {
-    if (it->second >= n) {
-      *off = it->first;
-      const int64_t rest = it->second - n;
-      const int64_t start = it->first + n;
-      S->free_ranges.erase(it);
-      if (rest > 0) S->free_ranges[start] = rest;
-      return true;
-    }
-  }
-  return false;
+  auto b = S->free_by_len.lower_bound({n, std::numeric_limits<int64_t>::min()});
+  if (b == S->free_by_len.end()) return false;
+  const int64_t len = b->first, at = b->second;
+  range_erase(S, S->free_ranges.find(at));
+  if (len > n) range_insert(S, at + n, len - n);
+  *off = at;
+  return true;
 }
 
 void pool_free(abp_server* S, int64_t off, int64_t n) {
-  auto it = S->free_ranges.emplace(off, n).first;
-  // merge with the next range
-  auto nx = std::next(it);
-  if (nx != S->free_ranges.end() && it->first + it->second == nx->first) {
-    it->second += nx->second;
-    S->free_ranges.erase(nx);
+  auto nx = S->free_ranges.lower_bound(off);
+  if (nx != S->free_ranges.end() && off + n == nx->first) {      // merge with the next range
+    n += nx->second;
+    auto after = std::next(nx);
+    range_erase(S, nx);
+    nx = after;
   }
-  // merge with the previous range
-  if (it != S->free_ranges.begin()) {
-    auto pv = std::prev(it);
-    if (pv->first + pv->second == it->first) {
-      pv->second += it->second;
-      S->free_ranges.erase(it);
+  if (nx != S->free_ranges.begin()) {                             // merge with the previous range
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      off = pv->first;
+      n += pv->second;
+      range_erase(S, pv);
     }
   }
+  range_insert(S, off, n);
 }
 
 abp_status finalize(abp_server* S) {
   if (!S->dirty) return ABP_OK;
-  const size_t na = S->hx0.size();
-  float** hp[4] = {&S->p_x0, &S->p_y0, &S->p_z0, &S->p_m};
-  float** dp[4] = {&S->m_x0, &S->m_y0, &S->m_z0, &S->m_m};
-  const std::vector<float>* src[4] = {&S->hx0, &S->hy0, &S->hz0, &S->hm};
-  for (int k = 0; k < 4; ++k) {
-    if (*hp[k]) { (void)hipHostFree(*hp[k]); *hp[k] = nullptr; }
-    SRV_TRY(hipHostMalloc((void**)hp[k], sizeof(float) * (na + 1), hipHostMallocMapped));
-    if (na) std::memcpy(*hp[k], src[k]->data(), sizeof(float) * na);
-    SRV_TRY(hipHostGetDevicePointer((void**)dp[k], *hp[k], 0));
-  }
   const size_t nl = S->lidx.size();
   if (S->d_lidx) { (void)hipFree(S->d_lidx); S->d_lidx = nullptr; }
   if (S->d_rx) { (void)hipFree(S->d_rx); S->d_rx = nullptr; }
@@ -208,7 +215,8 @@ void reset_residency(abp_server* S) {
     w.queue.clear();
   }
   S->free_ranges.clear();
-  if (S->pool_atoms > 0) S->free_ranges[0] = S->pool_atoms;
+  S->free_by_len.clear();
+  if (S->pool_atoms > 0) range_insert(S, 0, S->pool_atoms);
   S->lru.clear();
   S->admission.clear();
   S->ready.clear();
@@ -334,14 +342,15 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
   for (auto& sl : S->slots) {
     bool good = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-                hipHostMalloc((void**)&sl.h_desc, L.total, hipHostMallocDefault) == hipSuccess &&
-                hipMalloc((void**)&sl.d_desc, L.total) == hipSuccess &&
+                hipHostMalloc((void**)&sl.h_desc, L.total + kStageBytes0, hipHostMallocDefault) == hipSuccess &&
+                hipMalloc((void**)&sl.d_desc, L.total + kStageBytes0) == hipSuccess &&
                 hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocDefault) == hipSuccess &&
                 hipMalloc((void**)&sl.d_out, sizeof(double) * B * (2 * S->ncv + 1)) == hipSuccess;
     if (!good) {
       abp_server_destroy(S);
       return sfail(ABP_E_NOMEM, "cannot allocate per-stream batch buffers");
     }
+    sl.desc_cap = L.total + kStageBytes0;
     sl.reqs.reserve(B);
     sl.dep_slots.reserve(B);
     // Workspace for a full batch at the history's capacity (split shape), so
@@ -367,9 +376,6 @@ abp_status abp_server_destroy(abp_server* S) {
     if (sl.d_out) (void)hipFree(sl.d_out);
     if (sl.d_ws) (void)hipFree(sl.d_ws);
   }
-  float* hp[4] = {S->p_x0, S->p_y0, S->p_z0, S->p_m};
-  for (float* p : hp)
-    if (p) (void)hipHostFree(p);
   if (S->d_lidx) (void)hipFree(S->d_lidx);
   if (S->d_rx) (void)hipFree(S->d_rx);
   if (S->d_ry) (void)hipFree(S->d_ry);
@@ -418,15 +424,14 @@ abp_status abp_server_add_walker(abp_server* S, int32_t n_atoms, const float* x0
   if (rmsd && (!ref_x || !ref_y || !ref_z)) return sfail(ABP_E_INVAL, "RMSD needs reference positions");
   Walker w;
   w.n = n_atoms;
-  w.host_base = (int64_t)S->hx0.size();
+  w.img_base = (int64_t)S->himg.size();
+  w.entries = total;
   w.list_base = (int64_t)S->lidx.size();
   for (int q = 0; q < S->nlists; ++q) w.len[q] = list_len[q];
-  S->hx0.insert(S->hx0.end(), x0, x0 + n_atoms);
-  S->hy0.insert(S->hy0.end(), y0, y0 + n_atoms);
-  S->hz0.insert(S->hz0.end(), z0, z0 + n_atoms);
-  S->hm.insert(S->hm.end(), mass, mass + n_atoms);
   for (int64_t e = 0; e < total; ++e) {
-    S->lidx.push_back(list_idx[e]);
+    const int32_t i = list_idx[e];
+    S->himg.push_back(make_float4(x0[i], y0[i], z0[i], mass[i]));
+    S->lidx.push_back(i);
     S->lrx.push_back(ref_x ? ref_x[e] : 0.0f);
     S->lry.push_back(ref_y ? ref_y[e] : 0.0f);
     S->lrz.push_back(ref_z ? ref_z[e] : 0.0f);
@@ -542,13 +547,33 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
     Slot& sl = S->slots[free_slot];
     const int64_t nb = std::min<int64_t>((int64_t)S->ready.size(), S->desc.max_batch);
     DescLayout L(nb, S->nlists);
+    // Staging for the walkers admitted since their last batch; the slot is
+    // idle, so its buffers may be replaced when they are too small.
+    int64_t n_stage = 0;
+    for (int64_t j = 0; j < nb; ++j) {
+      const Walker& w = S->walkers[S->ready[j]];
+      if (w.fresh) n_stage += w.entries;
+    }
+    const size_t desc_bytes = L.total + (size_t)n_stage * sizeof(float4);
+    if (desc_bytes > sl.desc_cap) {
+      const size_t cap = std::max(desc_bytes, 2 * sl.desc_cap);
+      SRV_TRY(hipHostFree(sl.h_desc));
+      SRV_TRY(hipFree(sl.d_desc));
+      sl.h_desc = nullptr;
+      sl.d_desc = nullptr;
+      sl.desc_cap = 0;
+      SRV_TRY(hipHostMalloc((void**)&sl.h_desc, cap, hipHostMallocDefault));
+      SRV_TRY(hipMalloc((void**)&sl.d_desc, cap));
+      sl.desc_cap = cap;
+    }
     int64_t* d_atom_base = reinterpret_cast<int64_t*>(sl.h_desc + L.atom_base);
-    int64_t* d_host_base = reinterpret_cast<int64_t*>(sl.h_desc + L.host_base);
+    int64_t* d_stage_off = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
+    float4* h_stage = reinterpret_cast<float4*>(sl.h_desc + L.total);
+    int64_t spos = 0;
     int64_t* d_step = reinterpret_cast<int64_t*>(sl.h_desc + L.step);
     int64_t* d_dep = reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
     double* d_hgt = reinterpret_cast<double*>(sl.h_desc + L.dep_height);
     int32_t* d_n = reinterpret_cast<int32_t*>(sl.h_desc + L.n_atoms);
-    int32_t* d_fresh = reinterpret_cast<int32_t*>(sl.h_desc + L.fresh);
     int32_t* d_wid = reinterpret_cast<int32_t*>(sl.h_desc + L.walker);
     int32_t* d_lbeg = reinterpret_cast<int32_t*>(sl.h_desc + L.list_beg);
     int32_t* d_llen = reinterpret_cast<int32_t*>(sl.h_desc + L.list_len);
@@ -566,11 +591,15 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
       w.queue.pop_front();
       sl.reqs.push_back(r);
       d_atom_base[j] = w.atom_base;
-      d_host_base[j] = w.host_base;
+      d_stage_off[j] = -1;
+      if (w.fresh) {          // this walker's CV entries, in list order
+        d_stage_off[j] = spos;
+        std::memcpy(h_stage + spos, S->himg.data() + w.img_base, sizeof(float4) * (size_t)w.entries);
+        spos += w.entries;
+        w.fresh = false;
+      }
       d_step[j] = step[r];
       d_n[j] = w.n;
-      d_fresh[j] = w.fresh ? 1 : 0;
-      w.fresh = false;
       d_wid[j] = wid;
       int64_t lpos = w.list_base;
       for (int q = 0; q < S->nlists; ++q) {
@@ -607,23 +636,20 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
       if (hipMalloc(&sl.d_ws, want) != hipSuccess) return sfail(ABP_E_NOMEM, "cannot grow the batch workspace");
       sl.ws_bytes = want;
     }
-    SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total, hipMemcpyHostToDevice, sl.stream));
+    SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float4), hipMemcpyHostToDevice,
+                           sl.stream));
     abp::EngineArgs E;
     E.nb = nb;
     E.atom_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.atom_base);
     E.n_atoms = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_atoms);
-    E.host_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.host_base);
-    E.fresh = reinterpret_cast<const int32_t*>(sl.d_desc + L.fresh);
+    E.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
+    E.stage = reinterpret_cast<const float4*>(sl.d_desc + L.total);
     E.walker = reinterpret_cast<const int32_t*>(sl.d_desc + L.walker);
     E.step = reinterpret_cast<const int64_t*>(sl.d_desc + L.step);
     E.nlists = S->nlists;
     E.list_beg = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_beg);
     E.list_len = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_len);
     E.list_idx = S->d_lidx;
-    E.h_x0 = S->m_x0;
-    E.h_y0 = S->m_y0;
-    E.h_z0 = S->m_z0;
-    E.h_mass = S->m_m;
     E.amplitude = S->desc.amplitude;
     E.x = pool_array(S, 0);
     E.y = pool_array(S, 1);

@@ -7,12 +7,12 @@
 //   x = x0 + amplitude * u(walker, step, atom, coordinate),
 // where u in [-1, 1) comes from an integer hash (the "lowbias32" mixer,
 // C. Wellons, 2018). The base positions x0 are the walker's resident state:
-// when the walker was just admitted they and the masses are copied from
-// mapped host memory into the device pool, and afterwards read from there (the
-// bias path reads no atom but the CV atoms, so only those cross PCIe, once
-// per admission). The arithmetic uses explicitly rounded float operations so
-// a host can reproduce the positions bit for bit. This stands in for an MD
-// engine; it is not part of the method.
+// when the walker was just admitted, the host has staged them and the masses
+// of its CV atoms in the batch descriptor (one copy for the batch), and they
+// are stored into the device pool; later steps read them from there. The
+// arithmetic uses explicitly rounded float operations so a host can
+// reproduce the positions bit for bit. This stands in for an MD engine; it is
+// not part of the method.
 #include "abp_serve_internal.h"
 
 namespace abp {
@@ -33,15 +33,15 @@ __device__ __forceinline__ float unit_hash(uint32_t w, uint32_t step, uint32_t a
   return (float)(int32_t)((h >> 16) & 0xffffu) * (1.0f / 32768.0f) - 1.0f;
 }
 
-constexpr int kInFlight = 16;   // loads each thread keeps in flight (PCIe latency on admission)
+constexpr int kInFlight = 16;   // entries each thread handles per pass (their loads overlap)
 
 __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t base = E.atom_base[j];
   const int32_t n = E.n_atoms[j];
-  const int64_t hbase = E.host_base[j];
-  const bool fresh = E.fresh[j] != 0;
+  const int64_t soff = E.stage_off[j];
+  const bool fresh = soff >= 0;
   const uint32_t w = (uint32_t)E.walker[j];
   const uint32_t st = (uint32_t)E.step[j];
   // CV atoms of all lists, flattened: entry r of list q sits at r - start[q].
@@ -66,11 +66,12 @@ __global__ __launch_bounds__(kBlock) void k_engine_step(const EngineArgs E) {
     if (fresh) {                                    // uniform per block
 #pragma unroll
       for (int u = 0; u < kInFlight; ++u) {
-        const int64_t hg = hbase + (atom[u] < 0 ? 0 : atom[u]);   // atom 0 stands in: always valid
-        px[u] = E.h_x0[hg];
-        py[u] = E.h_y0[hg];
-        pz[u] = E.h_z0[hg];
-        pm[u] = E.h_mass[hg];
+        const int r = r0 + u * kBlock + tid;
+        const float4 v = E.stage[soff + (r < total ? r : 0)];   // entry 0 stands in: always staged
+        px[u] = v.x;
+        py[u] = v.y;
+        pz[u] = v.z;
+        pm[u] = v.w;
       }
     } else {
 #pragma unroll
