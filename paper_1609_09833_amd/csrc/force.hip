@@ -37,6 +37,7 @@
 // another with a barrier between them. Either way the sum per atom has a
 // fixed order. With the grid form of the bias the CV block interpolates,
 // transforms and finishes in the same launch.
+#include <climits>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -415,20 +416,57 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
   int badbits = 0;
   // Register arrays are only indexed with compile-time constants (dynamic
-  // indices would move them to scratch memory).
-  auto gather = [&](int r, Entry& out) {
-    out.gi = -1; out.li = 0; out.e = 0; out.m = 0.0f;
-    int li = -1, e = 0;
+  // indices would move them to scratch memory). A thread's cached entries are
+  // gathered in three passes, so that their loads overlap: list entry and
+  // atom index (with the previous index, for the order check), then the
+  // atom's position and mass (and the reference for RMSD), then the sums, in
+  // entry order.
+  struct Got {
+    int li, e;
+    int32_t i, ip;
+    float x, y, z, m, rx, ry, rz;
+  };
+  auto locate = [&](int r, Got& G) {
+    G.li = -1; G.e = 0; G.i = -1; G.ip = INT_MIN;
 #pragma unroll
     for (int q = 0; q < 2 * D; ++q)
-      if (r >= S.pos[q] && r < S.pos[q + 1]) { li = q; e = S.lb[q] + (r - S.pos[q]); }
+      if (r >= S.pos[q] && r < S.pos[q + 1]) { G.li = q; G.e = S.lb[q] + (r - S.pos[q]); }
+    if (G.li < 0) return;
+    G.i = A.list_idx[G.e];
+    if (S.kind[G.li >> 1] != ABP_CV_TORSION && G.e > S.lb[G.li]) G.ip = A.list_idx[G.e - 1];
+  };
+  // The loads of fetch are not branched per entry (a branch around each would
+  // make the compiler wait for all loads in flight at its join): an entry
+  // without a valid atom reads the walker's first atom and list entry 0
+  // instead, in bounds, and consume ignores those values.
+  bool any_ref = A.ref_x && A.ref_y && A.ref_z;
+  {
+    bool rm = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) rm = rm || S.kind[a] == ABP_CV_RMSD_OFF;
+    any_ref = any_ref && rm;
+  }
+  auto fetch = [&](Got& G) {
+    G.x = 0.0f; G.y = 0.0f; G.z = 0.0f; G.m = 0.0f; G.rx = 0.0f; G.ry = 0.0f; G.rz = 0.0f;
+    const bool ok = G.li >= 0 && G.i >= 0 && G.i < natoms;
+    if (natoms >= 1) {                                   // uniform
+      const int64_t g = base + (ok ? G.i : 0);
+      G.x = A.x[g]; G.y = A.y[g]; G.z = A.z[g]; G.m = A.mass[g];
+    }
+    if (any_ref) {                                       // uniform; RMSD lists are not empty
+      const int e = G.li >= 0 ? G.e : 0;
+      G.rx = A.ref_x[e]; G.ry = A.ref_y[e]; G.rz = A.ref_z[e];
+    }
+  };
+  auto consume = [&](int r, const Got& G, Entry& out) {
+    out.gi = -1; out.li = 0; out.e = 0; out.m = 0.0f;
+    const int li = G.li, e = G.e;
     if (li < 0) return;
     const int kind = S.kind[li >> 1];
-    const int32_t i = A.list_idx[e];
+    const int32_t i = G.i;
     if (i < 0 || i >= natoms) { badbits |= kErrIndex; return; }
-    if (kind != ABP_CV_TORSION && e > S.lb[li] && A.list_idx[e - 1] >= i) badbits |= kErrIndex;
-    const int64_t g = base + i;
-    const float x = A.x[g], y = A.y[g], z = A.z[g], m = A.mass[g];
+    if (G.ip >= i) badbits |= kErrIndex;                 // COM/RMSD lists must increase
+    const float x = G.x, y = G.y, z = G.z, m = G.m;
     if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(m)) badbits |= kErrNonfinite;
     if (kind == ABP_CV_COM_DIST) {
 #pragma unroll
@@ -440,7 +478,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
           acc[q * 4 + 3] += (double)m;
         }
     } else if (kind == ABP_CV_RMSD_OFF) {
-      const float rx = A.ref_x[e], ry = A.ref_y[e], rz = A.ref_z[e];
+      const float rx = G.rx, ry = G.ry, rz = G.rz;
       if (!isfinite(rx) || !isfinite(ry) || !isfinite(rz)) badbits |= kErrNonfinite;
       const double dx = (double)x - rx, dy = (double)y - ry, dz = (double)z - rz;
 #pragma unroll
@@ -456,18 +494,25 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
     if (r < kMaxCached) sh_list[r] = i;
     out.gi = i; out.li = li; out.e = e; out.m = m;
   };
+  {
+    Got G[kCache];
 #pragma unroll
-  for (int k = 0; k < kCache; ++k) {
-    const int r = k * kFBlock + tid;
-    ent[k].gi = -1;
-    ent[k].li = 0;
-    ent[k].e = 0;
-    ent[k].m = 0.0f;
-    if (r < total) gather(r, ent[k]);
+    for (int k = 0; k < kCache; ++k) {
+      G[k].li = -1; G[k].e = 0; G[k].i = -1; G[k].ip = INT_MIN;
+      const int r = k * kFBlock + tid;
+      if (r < total) locate(r, G[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) fetch(G[k]);
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) consume(k * kFBlock + tid, G[k], ent[k]);
   }
   for (int r = kMaxCached + tid; r < total; r += kFBlock) {
+    Got G;
+    locate(r, G);
+    fetch(G);
     Entry tmp;
-    gather(r, tmp);
+    consume(r, G, tmp);
   }
   if (badbits) atomicOr(&S.bad, badbits);
   acc[9 * D] = badbits ? 1.0 : 0.0;
