@@ -18,10 +18,12 @@
 // the batch was formed); deposits go to slots reserved in formation order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <limits>
 #include <list>
 #include <map>
@@ -44,7 +46,6 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
 
 constexpr int kMaxLists = 6;
 constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;   // ten FP32 pool arrays
-constexpr size_t kStageBytes0 = (size_t)1 << 20;   // initial staging area per stream (grows on demand)
 
 struct Walker {
   int32_t n = 0;
@@ -184,6 +185,33 @@ void pool_free(abp_server* S, int64_t off, int64_t n) {
     }
   }
   range_insert(S, off, n);
+}
+
+// Descriptor buffers of every stream, sized once per replay for the largest
+// staging a batch can need: the max_batch walkers with the most CV entries,
+// all just admitted (never more than all walkers' CV images together). The
+// slots must be idle.
+abp_status size_descriptors(abp_server* S) {
+  std::vector<int64_t> ent;
+  ent.reserve(S->walkers.size());
+  for (const auto& w : S->walkers) ent.push_back(w.entries);
+  const size_t b = std::min(ent.size(), (size_t)S->desc.max_batch);
+  std::partial_sort(ent.begin(), ent.begin() + b, ent.end(), std::greater<int64_t>());
+  int64_t most = 0;
+  for (size_t i = 0; i < b; ++i) most += ent[i];
+  const size_t need = DescLayout(S->desc.max_batch, S->nlists).total + (size_t)most * sizeof(float4);
+  for (auto& sl : S->slots) {
+    if (sl.desc_cap >= need) continue;
+    SRV_TRY(hipHostFree(sl.h_desc));
+    SRV_TRY(hipFree(sl.d_desc));
+    sl.h_desc = nullptr;
+    sl.d_desc = nullptr;
+    sl.desc_cap = 0;
+    SRV_TRY(hipHostMalloc((void**)&sl.h_desc, need, hipHostMallocDefault));
+    SRV_TRY(hipMalloc((void**)&sl.d_desc, need));
+    sl.desc_cap = need;
+  }
+  return ABP_OK;
 }
 
 abp_status finalize(abp_server* S) {
@@ -342,15 +370,15 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
   for (auto& sl : S->slots) {
     bool good = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-                hipHostMalloc((void**)&sl.h_desc, L.total + kStageBytes0, hipHostMallocDefault) == hipSuccess &&
-                hipMalloc((void**)&sl.d_desc, L.total + kStageBytes0) == hipSuccess &&
+                hipHostMalloc((void**)&sl.h_desc, L.total, hipHostMallocDefault) == hipSuccess &&
+                hipMalloc((void**)&sl.d_desc, L.total) == hipSuccess &&
                 hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocDefault) == hipSuccess &&
                 hipMalloc((void**)&sl.d_out, sizeof(double) * B * (2 * S->ncv + 1)) == hipSuccess;
     if (!good) {
       abp_server_destroy(S);
       return sfail(ABP_E_NOMEM, "cannot allocate per-stream batch buffers");
     }
-    sl.desc_cap = L.total + kStageBytes0;
+    sl.desc_cap = L.total;
     sl.reqs.reserve(B);
     sl.dep_slots.reserve(B);
     // Workspace for a full batch at the history's capacity (split shape), so
@@ -465,6 +493,8 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
     SRV_TRY(hipStreamSynchronize(sl.stream));
     sl.busy = false;
   }
+  st = size_descriptors(S);
+  if (st != ABP_OK) return st;
   S->launch_order.clear();
   reset_residency(S);
   S->dep_done.clear();
@@ -547,24 +577,16 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
     Slot& sl = S->slots[free_slot];
     const int64_t nb = std::min<int64_t>((int64_t)S->ready.size(), S->desc.max_batch);
     DescLayout L(nb, S->nlists);
-    // Staging for the walkers admitted since their last batch; the slot is
-    // idle, so its buffers may be replaced when they are too small.
-    int64_t n_stage = 0;
-    for (int64_t j = 0; j < nb; ++j) {
-      const Walker& w = S->walkers[S->ready[j]];
-      if (w.fresh) n_stage += w.entries;
-    }
-    const size_t desc_bytes = L.total + (size_t)n_stage * sizeof(float4);
-    if (desc_bytes > sl.desc_cap) {
-      const size_t cap = std::max(desc_bytes, 2 * sl.desc_cap);
-      SRV_TRY(hipHostFree(sl.h_desc));
-      SRV_TRY(hipFree(sl.d_desc));
-      sl.h_desc = nullptr;
-      sl.d_desc = nullptr;
-      sl.desc_cap = 0;
-      SRV_TRY(hipHostMalloc((void**)&sl.h_desc, cap, hipHostMallocDefault));
-      SRV_TRY(hipMalloc((void**)&sl.d_desc, cap));
-      sl.desc_cap = cap;
+    // Staging for the walkers admitted since their last batch (the buffers
+    // were sized for the worst case when the replay began).
+    {
+      int64_t n_stage = 0;
+      for (int64_t j = 0; j < nb; ++j) {
+        const Walker& w = S->walkers[S->ready[j]];
+        if (w.fresh) n_stage += w.entries;
+      }
+      if (L.total + (size_t)n_stage * sizeof(float4) > sl.desc_cap)
+        return sfail(ABP_E_DEVICE, "batch descriptor larger than sized (internal error)");
     }
     int64_t* d_atom_base = reinterpret_cast<int64_t*>(sl.h_desc + L.atom_base);
     int64_t* d_stage_off = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
