@@ -13,7 +13,8 @@
 //      base positions and masses of the CV atoms of walkers admitted since
 //      their last batch, gathered here), the engine step (those stored into
 //      the pool, CV-atom positions for this step, cleared CV-atom forces), the
-//      bias-force stages, the output download, an event.
+//      bias-force stages (they write the outputs straight into mapped host
+//      memory), an event.
 // Requests in one batch see the same history version (hills committed when
 // the batch was formed); deposits go to slots reserved in formation order.
 #include <hip/hip_runtime.h>
@@ -74,8 +75,8 @@ struct Slot {
   char* h_desc = nullptr;            // pinned descriptor, then the staged base positions
   char* d_desc = nullptr;
   size_t desc_cap = 0;               // bytes of h_desc and of d_desc
-  double* h_out = nullptr;           // pinned outputs: s[ncv][nb], V[nb], dV[ncv][nb]
-  double* d_out = nullptr;
+  double* h_out = nullptr;           // mapped pinned outputs: s[ncv][nb], V[nb], dV[ncv][nb]
+  double* m_out = nullptr;           // its device view: the bias-force launches write there directly
   void* d_ws = nullptr;              // bias_force workspace
   size_t ws_bytes = 0;
 };
@@ -372,8 +373,8 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
                 hipHostMalloc((void**)&sl.h_desc, L.total, hipHostMallocDefault) == hipSuccess &&
                 hipMalloc((void**)&sl.d_desc, L.total) == hipSuccess &&
-                hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocDefault) == hipSuccess &&
-                hipMalloc((void**)&sl.d_out, sizeof(double) * B * (2 * S->ncv + 1)) == hipSuccess;
+                hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocMapped) == hipSuccess &&
+                hipHostGetDevicePointer((void**)&sl.m_out, sl.h_out, 0) == hipSuccess;
     if (!good) {
       abp_server_destroy(S);
       return sfail(ABP_E_NOMEM, "cannot allocate per-stream batch buffers");
@@ -401,7 +402,6 @@ abp_status abp_server_destroy(abp_server* S) {
     if (sl.h_desc) (void)hipHostFree(sl.h_desc);
     if (sl.d_desc) (void)hipFree(sl.d_desc);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
-    if (sl.d_out) (void)hipFree(sl.d_out);
     if (sl.d_ws) (void)hipFree(sl.d_ws);
   }
   if (S->d_lidx) (void)hipFree(S->d_lidx);
@@ -708,14 +708,12 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
     A.n_visible_default = sl.version;
     A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(sl.d_desc + L.dep_slot) : nullptr;
     A.deposit_height = reinterpret_cast<const double*>(sl.d_desc + L.dep_height);
-    A.s = sl.d_out;
-    A.V = sl.d_out + ncv * nb;
-    A.dVds = sl.d_out + (ncv + 1) * nb;
+    A.s = sl.m_out;
+    A.V = sl.m_out + ncv * nb;
+    A.dVds = sl.m_out + (ncv + 1) * nb;
     A.prec = S->desc.prec;
     A.err = S->cv.err;
     SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
-    SRV_TRY(hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * nb * (2 * ncv + 1), hipMemcpyDeviceToHost,
-                           sl.stream));
     SRV_TRY(hipEventRecord(sl.done, sl.stream));
     sl.busy = true;
     S->launch_order.push_back(free_slot);
