@@ -243,6 +243,7 @@ abp_status force_workspace(abp_ctx* ctx, int64_t nw, int nbw) {
     ctx->fws_bytes = 0;
     if (hipMalloc(&ctx->fws, pb) != hipSuccess) return fail(ABP_E_NOMEM, "cannot allocate bias_force workspace");
     ctx->fws_bytes = pb;
+    HIP_TRY(hipMemset(ctx->fws, 0, pb));
   }
   return ABP_OK;
 }

@@ -133,8 +133,11 @@ constexpr int kChunkHills = 64;
 __host__ __device__ inline int64_t force_chunks(int64_t nvis) { return (nvis + kChunkHills - 1) / kChunkHills; }
 
 // Chunk partials per walker for a history of `committed` hills; whether a
-// launch of nw walkers takes the split shape (which needs the workspace); the
-// workspace bytes of that shape (CV state, cached atom lists, partials).
+// launch of nw walkers takes the split or chained shape (which need the
+// workspace); the workspace bytes of those shapes. A workspace must be zeroed
+// when allocated (its first kForceArrivedBytes hold counters that the chained
+// launch leaves at zero).
+constexpr size_t kForceArrivedBytes = 256;
 int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only);
 bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only);
 size_t force_workspace_bytes(int64_t nw, int nbw, int ndim);

@@ -37,6 +37,7 @@
 // another with a barrier between them. Either way the sum per atom has a
 // fixed order. With the grid form of the bias the CV block interpolates,
 // transforms and finishes in the same launch.
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -61,6 +62,16 @@ constexpr double kMinCross2 = 1e-24;    // collinear torsion atoms
 // launches, whose sum launch reads each hill record once per 64 walkers
 // instead of once per walker (the result does not depend on the choice).
 constexpr int64_t kFusedMaxHills = 16384;
+// Batches of up to kChainMaxWalkers walkers take the chained launch instead
+// of the split launches (same decomposition and order, so the same results):
+// one launch, but every block of a walker recomputes its CV. That pays for
+// one or two walkers (measured: 100,000 hills, one walker, 25.9 -> 21.9 us);
+// for the serving loop's batches of a few walkers on concurrent streams the
+// redundant CV gathers cost more than the two launches they save (p50 at
+// 200,000 hills 90 -> 131 us). kChainCounters bounds the batches that the
+// ABP_FORCE_SHAPE=chain override can send through it.
+constexpr int64_t kChainMaxWalkers = 2;
+constexpr int64_t kChainCounters = 64;
 
 // CV state of one walker, held in LDS by a block and in the workspace
 // between the launches of the split shape.
@@ -94,6 +105,7 @@ struct FArgs {
   int* sbad;                   // [nw] nonzero: walker invalid (split shape)
   float2* part32;              // [nw][pmax][D+1] partial sums (hi, lo), FP32 modes
   double* part64;              // the same buffer, FP64 mode
+  unsigned* arrived;           // [nw] blocks of the chained launch done with their chunks (0 between launches)
 };
 
 __device__ __forceinline__ void list_bounds(const ForceArgs& A, int64_t w, int q, int& b, int& n) {
@@ -1008,13 +1020,120 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
 }
 
 // ---------------------------------------------------------------------------
-// Launch selection.
+// Chained shape (few walkers, long history), one launch: block (g, w)
+// computes walker w's CV, the sums of chunks g * kFBlock + t (thread t; each
+// chunk exactly as the fused launch sums it) into the workspace, and counts
+// itself in F.arrived[w]; the walker's last block to arrive merges every chunk
+// sum in the fused launch's order and finishes (transform, outputs, deposit,
+// chain rule), then resets the counter for the next launch. Every block
+// arrives, also for an invalid walker, and no block waits for another.
 // ---------------------------------------------------------------------------
 template <int D, int PMASK, int KERN, bool FP64>
-hipError_t go_direct(const FArgs& F, bool fused, hipStream_t stream) {
+__global__ __launch_bounds__(kFBlock) void k_force_chain(const FArgs F) {
+  constexpr int N = D + 1;
+  const ForceArgs& A = F.A;
+  const Consts& K = F.K;
+  const int64_t w = blockIdx.y;
+  const int tid = threadIdx.x;
+  __shared__ double red[(kFBlock / 64) * (9 * D + 1)];
+  __shared__ CvState S;
+  __shared__ double tpos[kMaxTors][4][3];
+  __shared__ int sh_list[kMaxCached];
+  __shared__ int last;
+  Entry ent[kCache];
+  const bool ok = cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list);   // uniform
+  const int64_t nvis = walker_nvis(F, w);
+  const int64_t nch = force_chunks(nvis);
+  const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
+  const int64_t c = (int64_t)blockIdx.x * kFBlock + tid;
+  if (ok && c < nch) {
+    const int n = chunk_terms(nvis, c);
+    const int64_t at = (w * F.pmax + c) * N;
+    if constexpr (FP64) {
+      double tq[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) tq[i] = work64(K, i, eval_coord(K, i, S.s[i]));
+      double pv[N];
+      partial_f64<D, PMASK, KERN, false>(K, tq, c * kChunkHills, n, n, [&](int64_t k) { return hill64(F, D, k); }, pv);
+#pragma unroll
+      for (int r = 0; r < N; ++r) F.part64[at + r] = pv[r];
+    } else {
+      uint32_t qw[D];
+      float kf[D], ua[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        qw[i] = work32(K, i, eval_coord(K, i, S.s[i]));
+        kf[i] = K.kf32[i];
+        ua[i] = K.ua32[i];
+      }
+      const int4* recs = F.H.rec32;
+      float ph[N], pl[N];
+      partial_f32<D, PMASK, KERN, false>(qw, kf, ua, K.pl32, comp, c * kChunkHills, n, n,
+                                         [&](int64_t k) { return recs[k]; }, ph, pl);
+#pragma unroll
+      for (int r = 0; r < N; ++r) F.part32[at + r] = make_float2(ph[r], pl[r]);
+    }
+  }
+  // arrival: the chunk sums are made visible before the count
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned before = atomicAdd(&F.arrived[w], 1u);
+    last = before == gridDim.x - 1 ? 1 : 0;
+    if (last) atomicExch(&F.arrived[w], 0u);   // every block of the walker has arrived
+  }
+  __syncthreads();
+  if (!last || !ok) return;
+  __threadfence();
+  float hi[N], lo[N];
+  double v64[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) { hi[r] = 0.0f; lo[r] = 0.0f; v64[r] = 0.0; }
+  for (int64_t c0 = tid; c0 < nch; c0 += kMergeBatch * kFBlock) {
+    float ph[kMergeBatch][N], pl[kMergeBatch][N];
+    double pv[kMergeBatch][N];
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u) {
+      const int64_t cc = c0 + (int64_t)u * kFBlock;
+      const int64_t at = (w * F.pmax + (cc < nch ? cc : c0)) * N;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        if (FP64) {
+          pv[u][r] = F.part64[at + r];
+          ph[u][r] = 0.0f;
+          pl[u][r] = 0.0f;
+        } else {
+          const float2 q = F.part32[at + r];
+          ph[u][r] = q.x;
+          pl[u][r] = q.y;
+          pv[u][r] = 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u)
+      if (c0 + (int64_t)u * kFBlock < nch) merge_part<N, FP64>(hi, lo, v64, ph[u], pl[u], pv[u], comp);
+  }
+  if (FP64) block_sum<N, kFBlock>(v64, red);
+  else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+}
+
+// ---------------------------------------------------------------------------
+// Launch selection.
+// ---------------------------------------------------------------------------
+enum { kShapeFused = 0, kShapeSplit = 1, kShapeChain = 2 };
+
+template <int D, int PMASK, int KERN, bool FP64>
+hipError_t go_direct(const FArgs& F, int shape, hipStream_t stream) {
   const dim3 walkers((unsigned)F.A.nw);
-  if (fused) {
+  if (shape == kShapeFused) {
     hipLaunchKernelGGL((k_force_fused<D, PMASK, KERN, FP64>), walkers, dim3(kFBlock), 0, stream, F);
+    return hipGetLastError();
+  }
+  if (shape == kShapeChain) {
+    const dim3 grid((unsigned)std::max<int64_t>(1, (F.pmax + kFBlock - 1) / kFBlock), (unsigned)F.A.nw);
+    hipLaunchKernelGGL((k_force_chain<D, PMASK, KERN, FP64>), grid, dim3(kFBlock), 0, stream, F);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_cv_stage<D, kStageSum>), walkers, dim3(kFBlock), 0, stream, F);
@@ -1027,23 +1146,23 @@ hipError_t go_direct(const FArgs& F, bool fused, hipStream_t stream) {
 }
 
 template <int D, int KERN, bool FP64>
-hipError_t direct_by_mask(int mask, const FArgs& F, bool fused, hipStream_t stream) {
+hipError_t direct_by_mask(int mask, const FArgs& F, int shape, hipStream_t stream) {
   switch (mask) {
-    case 0: return go_direct<D, 0, KERN, FP64>(F, fused, stream);
-    case 1: return go_direct<D, 1, KERN, FP64>(F, fused, stream);
-    case 2: if constexpr (D >= 2) return go_direct<D, 2, KERN, FP64>(F, fused, stream); break;
-    case 3: if constexpr (D >= 2) return go_direct<D, 3, KERN, FP64>(F, fused, stream); break;
-    case 4: if constexpr (D >= 3) return go_direct<D, 4, KERN, FP64>(F, fused, stream); break;
-    case 5: if constexpr (D >= 3) return go_direct<D, 5, KERN, FP64>(F, fused, stream); break;
-    case 6: if constexpr (D >= 3) return go_direct<D, 6, KERN, FP64>(F, fused, stream); break;
-    case 7: if constexpr (D >= 3) return go_direct<D, 7, KERN, FP64>(F, fused, stream); break;
+    case 0: return go_direct<D, 0, KERN, FP64>(F, shape, stream);
+    case 1: return go_direct<D, 1, KERN, FP64>(F, shape, stream);
+    case 2: if constexpr (D >= 2) return go_direct<D, 2, KERN, FP64>(F, shape, stream); break;
+    case 3: if constexpr (D >= 2) return go_direct<D, 3, KERN, FP64>(F, shape, stream); break;
+    case 4: if constexpr (D >= 3) return go_direct<D, 4, KERN, FP64>(F, shape, stream); break;
+    case 5: if constexpr (D >= 3) return go_direct<D, 5, KERN, FP64>(F, shape, stream); break;
+    case 6: if constexpr (D >= 3) return go_direct<D, 6, KERN, FP64>(F, shape, stream); break;
+    case 7: if constexpr (D >= 3) return go_direct<D, 7, KERN, FP64>(F, shape, stream); break;
     default: break;
   }
   return hipErrorInvalidValue;
 }
 
 template <int D>
-hipError_t launch_d(int mask, const FArgs& F, bool fused, hipStream_t stream) {
+hipError_t launch_d(int mask, const FArgs& F, int shape, hipStream_t stream) {
   const dim3 walkers((unsigned)F.A.nw);
   if (F.A.cv_only) {
     hipLaunchKernelGGL((k_cv_stage<D, kStageCV>), walkers, dim3(kFBlock), 0, stream, F);
@@ -1055,10 +1174,23 @@ hipError_t launch_d(int mask, const FArgs& F, bool fused, hipStream_t stream) {
   }
   const bool gauss = F.K.kernel == ABP_K_GAUSS;
   if (F.A.prec == ABP_PREC_FP64)
-    return gauss ? direct_by_mask<D, ABP_K_GAUSS, true>(mask, F, fused, stream)
-                 : direct_by_mask<D, ABP_K_COMPACT, true>(mask, F, fused, stream);
-  return gauss ? direct_by_mask<D, ABP_K_GAUSS, false>(mask, F, fused, stream)
-               : direct_by_mask<D, ABP_K_COMPACT, false>(mask, F, fused, stream);
+    return gauss ? direct_by_mask<D, ABP_K_GAUSS, true>(mask, F, shape, stream)
+                 : direct_by_mask<D, ABP_K_COMPACT, true>(mask, F, shape, stream);
+  return gauss ? direct_by_mask<D, ABP_K_GAUSS, false>(mask, F, shape, stream)
+               : direct_by_mask<D, ABP_K_COMPACT, false>(mask, F, shape, stream);
+}
+
+// The launch shape of a direct-sum bias_force: fused (short histories), else
+// chained (one or two walkers) or split. ABP_FORCE_SHAPE=fused|split|chain
+// overrides the choice (for tests and tuning; chain applies to batches of up
+// to kChainCounters); all three give the same results.
+int direct_shape(int64_t nw, int64_t committed) {
+  const char* env = std::getenv("ABP_FORCE_SHAPE");
+  if (env && std::strcmp(env, "fused") == 0) return kShapeFused;
+  if (env && std::strcmp(env, "split") == 0) return kShapeSplit;
+  if (env && std::strcmp(env, "chain") == 0) return nw <= kChainCounters ? kShapeChain : kShapeSplit;
+  if (committed <= kFusedMaxHills) return kShapeFused;
+  return nw <= kChainMaxWalkers ? kShapeChain : kShapeSplit;
 }
 
 }  // namespace
@@ -1070,22 +1202,22 @@ int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only) {
 
 bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only) {
   if (use_grid || cv_only) return false;
-  (void)nw;
-  // ABP_FORCE_SHAPE=fused|split overrides the choice (for tests and tuning).
-  if (const char* env = std::getenv("ABP_FORCE_SHAPE")) {
-    if (std::strcmp(env, "fused") == 0) return false;
-    if (std::strcmp(env, "split") == 0) return true;
-  }
-  return committed > kFusedMaxHills;
+  return direct_shape(nw, committed) != kShapeFused;
 }
+
+// Layout: the chained shape's arrival counters (a fixed region at the start,
+// which no other shape writes, so they stay zero between launches whatever
+// the batch sizes), CV state, cached entries, coordinates and flags (split
+// shape), chunk partials (both).
+static_assert(kChainCounters * sizeof(unsigned) <= kForceArrivedBytes, "counter region too small");
 
 size_t force_workspace_bytes(int64_t nw, int nbw, int ndim) {
   if (nw <= 0) return 0;
   const size_t st = (size_t)nw * sizeof(CvState);
   const size_t en = (size_t)nw * kMaxCached * sizeof(Entry);
-  const size_t pa = (size_t)nw * (size_t)nbw * (size_t)(ndim + 1) * 8;   // float2 or double
   const size_t sc = (size_t)nw * (3 * sizeof(double) + sizeof(int));
-  return (st + 255) / 256 * 256 + (en + 255) / 256 * 256 + (sc + 255) / 256 * 256 + pa;
+  const size_t pa = (size_t)nw * (size_t)nbw * (size_t)(ndim + 1) * 8;   // float2 or double
+  return kForceArrivedBytes + (st + 255) / 256 * 256 + (en + 255) / 256 * 256 + (sc + 255) / 256 * 256 + pa;
 }
 
 hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* workspace,
@@ -1104,9 +1236,11 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
   F.part32 = nullptr;
   F.part64 = nullptr;
   const bool split = force_uses_workspace(A.nw, F.committed, A.use_grid, A.cv_only);
+  F.arrived = nullptr;
   if (split) {
     if (!workspace) return hipErrorInvalidValue;
-    char* p = static_cast<char*>(workspace);
+    F.arrived = static_cast<unsigned*>(workspace);
+    char* p = static_cast<char*>(workspace) + kForceArrivedBytes;
     const size_t st = ((size_t)A.nw * sizeof(CvState) + 255) / 256 * 256;
     const size_t en = ((size_t)A.nw * kMaxCached * sizeof(Entry) + 255) / 256 * 256;
     const size_t sc = ((size_t)A.nw * (3 * sizeof(double) + sizeof(int)) + 255) / 256 * 256;
@@ -1117,12 +1251,13 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
     F.part32 = reinterpret_cast<float2*>(p + st + en + sc);
     F.part64 = reinterpret_cast<double*>(p + st + en + sc);
   }
+  const int shape = (A.use_grid || A.cv_only) ? kShapeFused : (split ? direct_shape(A.nw, F.committed) : kShapeFused);
   int mask = 0;
   for (int i = 0; i < K.ndim; ++i) mask |= (K.periodic[i] ? 1 : 0) << i;
   switch (K.ndim) {
-    case 1: return launch_d<1>(mask, F, !split, stream);
-    case 2: return launch_d<2>(mask, F, !split, stream);
-    case 3: return launch_d<3>(mask, F, !split, stream);
+    case 1: return launch_d<1>(mask, F, shape, stream);
+    case 2: return launch_d<2>(mask, F, shape, stream);
+    case 3: return launch_d<3>(mask, F, shape, stream);
     default: return hipErrorInvalidValue;
   }
 }

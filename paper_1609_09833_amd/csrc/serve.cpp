@@ -385,8 +385,13 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     // Workspace for a full batch at the history's capacity (split shape), so
     // the loop never reallocates; it still grows on demand if this fails.
     const size_t full = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
-    if (full <= ((size_t)1 << 30) && hipMalloc(&sl.d_ws, full) == hipSuccess) sl.ws_bytes = full;
-    else sl.d_ws = nullptr;
+    if (full <= ((size_t)1 << 30) && hipMalloc(&sl.d_ws, full) == hipSuccess &&
+        hipMemset(sl.d_ws, 0, full) == hipSuccess)
+      sl.ws_bytes = full;
+    else if (sl.d_ws) {
+      (void)hipFree(sl.d_ws);
+      sl.d_ws = nullptr;
+    }
   }
   *out = S;
   return ABP_OK;
@@ -644,7 +649,7 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
       sl.dep_slots.push_back(slot);
     }
     sl.nb = nb;
-    // Workspace for this batch's partial sums (split shape); grows with the history
+    // Workspace for this batch's partial sums (split or chained shape); grows with the history
     // (the slot is idle here, so freeing its old buffer is safe).
     const size_t need = abp::force_uses_workspace(nb, sl.version, 0, 0)
                             ? abp::force_workspace_bytes(nb, abp::force_blocks_per_walker(sl.version, 0, 0), ncv)
@@ -656,6 +661,7 @@ abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, co
       const size_t want = std::max(need, abp::force_workspace_bytes(
           S->desc.max_batch, abp::force_blocks_per_walker(2 * sl.version + 4096, 0, 0), ncv));
       if (hipMalloc(&sl.d_ws, want) != hipSuccess) return sfail(ABP_E_NOMEM, "cannot grow the batch workspace");
+      SRV_TRY(hipMemset(sl.d_ws, 0, want));
       sl.ws_bytes = want;
     }
     SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float4), hipMemcpyHostToDevice,

@@ -45,7 +45,7 @@ def _clean_run(lib, ctx, wk):
     return host(s), host(V), host(dV), host(dw.fx)
 
 
-@pytest.mark.parametrize("shape", ["fused", "split"])
+@pytest.mark.parametrize("shape", ["fused", "split", "chain"])
 def test_bad_atom_index_isolated(lib, small, shape, monkeypatch):
     wk, spec, hills = small
     monkeypatch.setenv("ABP_FORCE_SHAPE", shape)

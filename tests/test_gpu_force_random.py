@@ -2,7 +2,7 @@
 fixed-case tests cover 2), every CV kind in every position (COM distance,
 torsion, offset RMSD), walkers of uneven size, COM groups that sometimes
 share atoms (the general chain rule), Gaussian and compact hills, plain and
-mABP, the fused, split and grid launch shapes, FP32 + Kahan and FP64."""
+mABP, the fused, split, chained and grid launch shapes, FP32 + Kahan and FP64."""
 import dataclasses
 
 import numpy as np
@@ -88,7 +88,7 @@ def _case(seed):
     cen = np.vstack([rng.uniform(lo[i], hi[i], nh) for i in range(D)]) if nh else np.zeros((D, 0))
     hills = W.Hills(cen, rng.uniform(0.1, 1.2, nh))
     wk = _walkers(rng, kinds, int(rng.integers(1, 40)))
-    shape = ("fused", "split", "grid")[(seed // 3) % 3]
+    shape = ("fused", "split", "chain", "grid")[(seed // 3) % 4]
     prec = int(rng.choice([0, 2]))          # ABP_PREC_FP32_KAHAN, ABP_PREC_FP64
     return spec, hills, wk, shape, prec
 

@@ -21,10 +21,12 @@ def lib():
     return abp
 
 
-@pytest.mark.parametrize("n_hills", [3000, 20000])          # fused and split launch shapes
+@pytest.mark.parametrize("n_hills,shape", [(3000, None), (20000, None), (20000, "chain")])   # fused, split, chained
 @pytest.mark.parametrize("mode", ["direct", "grid"])
-def test_bias_force_graph_replays(lib, n_hills, mode):
+def test_bias_force_graph_replays(lib, n_hills, shape, mode, monkeypatch):
     import torch
+    if shape:
+        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)     # its counters must be back at zero after every replay
     wk = W.ligand_pocket_walkers(seed=71, n_walkers=64, atoms_lo=1000, atoms_hi=3000)
     spec, hills = W.ligand_pocket_hills(seed=72, n_hills=n_hills)
     ctx = lib.Context(spec, hills.n)

@@ -368,9 +368,10 @@ def test_c3_alone_equals_in_the_mix(c3):
 
 
 # ---------------------------------------------------------------------------
-# launch shapes: many walkers take the fused launch, few walkers with a long
-# history the split launches; both compute the same decomposition of the sum,
-# so they agree bitwise, also with a different n_visible per walker
+# launch shapes: short histories take the fused launch, long ones the split
+# launches or, for batches of up to 64 walkers, the chained launch; all compute
+# the same decomposition of the sum in the same order, so they agree bitwise,
+# also with a different n_visible per walker
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def shape_walkers():
@@ -417,23 +418,24 @@ def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, mo
     check_bound("shape V", V, ref[1], sA0, tol, floor)
     check_bound("shape dVds", dV, ref[2], sA, tol, floor * 1e4 * max(1.0, 1.0 / min(spec.width[:2]) ** 2))
     assert V[0] == 0.0 and np.all(dV[:, 0] == 0.0)        # no visible hills
-    # split: a 64-walker batch (mixed partial counts in a wave) and single walkers
-    monkeypatch.setenv("ABP_FORCE_SHAPE", "split")
-    d64 = abp.DeviceWalkers(_first_walkers(wk, 64))
-    s64, V64, dV64 = abp.bias_force(ctx, d64, prec=prec, n_visible=nvis[:64])
-    assert np.array_equal(host(s64), s[:, :64])
-    assert np.array_equal(host(V64), V[:64])
-    assert np.array_equal(host(dV64), dV[:, :64])
-    n64 = int(wk.atom_base[63] + wk.n_atoms[63])
-    assert np.array_equal(host(d64.fx), F[0][:n64])
-    for w in (0, 5, 77, 255):
-        d1 = abp.DeviceWalkers(W.single_walker(wk, w))
-        s1, V1, dV1 = abp.bias_force(ctx, d1, prec=prec, n_visible=nvis[w:w + 1])
-        assert np.array_equal(host(s1)[:, 0], s[:, w])
-        assert np.array_equal(host(V1)[0], V[w])
-        assert np.array_equal(host(dV1)[:, 0], dV[:, w])
-        b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
-        assert np.array_equal(host(d1.fy), F[1][b:b + n])
+    # split and chained: a 64-walker batch (mixed partial counts in a wave) and single walkers
+    for shape in ("split", "chain"):
+        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+        d64 = abp.DeviceWalkers(_first_walkers(wk, 64))
+        s64, V64, dV64 = abp.bias_force(ctx, d64, prec=prec, n_visible=nvis[:64])
+        assert np.array_equal(host(s64), s[:, :64]), shape
+        assert np.array_equal(host(V64), V[:64]), shape
+        assert np.array_equal(host(dV64), dV[:, :64]), shape
+        n64 = int(wk.atom_base[63] + wk.n_atoms[63])
+        assert np.array_equal(host(d64.fx), F[0][:n64]), shape
+        for w in (0, 5, 77, 255):
+            d1 = abp.DeviceWalkers(W.single_walker(wk, w))
+            s1, V1, dV1 = abp.bias_force(ctx, d1, prec=prec, n_visible=nvis[w:w + 1])
+            assert np.array_equal(host(s1)[:, 0], s[:, w]), shape
+            assert np.array_equal(host(V1)[0], V[w]), shape
+            assert np.array_equal(host(dV1)[:, 0], dV[:, w]), shape
+            b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
+            assert np.array_equal(host(d1.fy), F[1][b:b + n]), shape
     monkeypatch.delenv("ABP_FORCE_SHAPE")
     d2 = abp.DeviceWalkers(W.single_walker(wk, 3))           # the default shape for this history
     s2, V2, _ = abp.bias_force(ctx, d2, prec=prec, n_visible=nvis[3:4])
