@@ -218,11 +218,14 @@ abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* wa
  * written to that history slot, which must have been reserved with
  * abp_reserve and is made visible by abp_commit.
  * Launches: one for the grid form and for histories of up to 16,384 hills;
- * three (CV, hill sum, finish) for longer ones, which use a workspace the
- * context allocates on first need (the environment variable
- * ABP_FORCE_SHAPE=fused|split forces one shape). A walker's result is bitwise
- * the same in any batch and either shape. Once the workspace exists the call
- * enqueues kernels only, so it can be captured in a HIP graph. */
+ * for longer ones three (CV, hill sum, finish) or, for one or two walkers,
+ * one chained launch; both use a workspace the context allocates and clears
+ * on first need (the environment variable ABP_FORCE_SHAPE=fused|split|chain
+ * forces one shape, chain for up to 64 walkers). A walker's result is
+ * bitwise the same in any batch and any shape. Once the workspace exists the
+ * call enqueues kernels only, so it can be captured in a HIP graph. Calls
+ * that share a context's workspace must not run concurrently on different
+ * streams. */
 abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
                       const abp_walkers* walkers, const int64_t* n_visible,
                       const int64_t* deposit_slot, const double* deposit_height,
