@@ -295,14 +295,14 @@ def serving_leg(abp, W, torch, window_s=1.0):
     res = {}
     n_win = int(rate * window_s)
     budget = 512 << 20
-    srv = server(budget, 1024, 3)
+    srv = server(budget, 1024, 2)          # two batches in flight: the lowest p99 in a sweep of 2, 3, 4, 6
     run(srv, "warm-up (not reported)", n_win // 5, 99)     # first launches, cold pool
     for i, hist in enumerate((0, 100_000, 200_000)):
         seed_to(hist)
         res[f"hist{hist // 1000}k_budget512MiB"] = run(srv, f"{hist} hills, 512 MiB", n_win, 100 + i)
     res["hist200k_budget512MiB_saturated"] = run(srv, "saturated", n_win, 110, req_rate=1e12)
     srv.close()
-    srv = server(8 << 30, 1024, 3)
+    srv = server(8 << 30, 1024, 2)
     res["hist200k_unlimited"] = run(srv, "200k hills, all resident", n_win, 120)
     srv.close()
     srv = server(8 << 30, 1, 4)
