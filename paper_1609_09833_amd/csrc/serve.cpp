@@ -25,15 +25,14 @@
 #include <cstring>
 #include <deque>
 #include <functional>
-#include <limits>
 #include <list>
 #include <map>
 #include <new>
-#include <set>
 #include <string>
 #include <vector>
 
 #include "abp_serve_internal.h"
+#include "range_pool.h"
 
 namespace {
 
@@ -129,10 +128,8 @@ struct abp_server {
   // device atom pools
   int64_t pool_atoms = 0;
   float* d_pool = nullptr;           // 10 arrays of pool_atoms floats
-  // free atom ranges of the pools, by offset (for merging) and by length
-  // (best fit in O(log n): admissions are frequent and the pools fragment)
-  std::map<int64_t, int64_t> free_ranges;            // offset -> length
-  std::set<std::pair<int64_t, int64_t>> free_by_len; // (length, offset)
+  abp::RangePool free_atoms;         // free atom ranges of the pools (best fit: admissions are
+                                     // frequent and the pools fragment)
   std::list<int32_t> lru;            // idle resident walkers, least recent first
   std::deque<int32_t> admission;     // walkers waiting for memory
   std::deque<int32_t> ready;         // resident, idle, with a request
@@ -148,45 +145,9 @@ namespace {
 
 float* pool_array(abp_server* S, int which) { return S->d_pool + (int64_t)which * S->pool_atoms; }
 
-void range_insert(abp_server* S, int64_t off, int64_t n) {
-  S->free_ranges.emplace(off, n);
-  S->free_by_len.emplace(n, off);
-}
+bool pool_alloc(abp_server* S, int64_t n, int64_t* off) { return S->free_atoms.alloc(n, off); }
 
-void range_erase(abp_server* S, std::map<int64_t, int64_t>::iterator it) {
-  S->free_by_len.erase({it->second, it->first});
-  S->free_ranges.erase(it);
-}
-
-// Best fit: the shortest free range that holds n atoms (lowest offset among equals).
-bool pool_alloc(abp_server* S, int64_t n, int64_t* off) {
-  auto b = S->free_by_len.lower_bound({n, std::numeric_limits<int64_t>::min()});
-  if (b == S->free_by_len.end()) return false;
-  const int64_t len = b->first, at = b->second;
-  range_erase(S, S->free_ranges.find(at));
-  if (len > n) range_insert(S, at + n, len - n);
-  *off = at;
-  return true;
-}
-
-void pool_free(abp_server* S, int64_t off, int64_t n) {
-  auto nx = S->free_ranges.lower_bound(off);
-  if (nx != S->free_ranges.end() && off + n == nx->first) {      // merge with the next range
-    n += nx->second;
-    auto after = std::next(nx);
-    range_erase(S, nx);
-    nx = after;
-  }
-  if (nx != S->free_ranges.begin()) {                             // merge with the previous range
-    auto pv = std::prev(nx);
-    if (pv->first + pv->second == off) {
-      off = pv->first;
-      n += pv->second;
-      range_erase(S, pv);
-    }
-  }
-  range_insert(S, off, n);
-}
+void pool_free(abp_server* S, int64_t off, int64_t n) { S->free_atoms.free(off, n); }
 
 // Descriptor buffers of every stream, sized once per replay for the largest
 // staging a batch can need: the max_batch walkers with the most CV entries,
@@ -243,9 +204,7 @@ void reset_residency(abp_server* S) {
     w.inflight = w.waiting_admission = w.in_ready = w.fresh = w.in_lru = false;
     w.queue.clear();
   }
-  S->free_ranges.clear();
-  S->free_by_len.clear();
-  if (S->pool_atoms > 0) range_insert(S, 0, S->pool_atoms);
+  S->free_atoms.reset(S->pool_atoms);
   S->lru.clear();
   S->admission.clear();
   S->ready.clear();

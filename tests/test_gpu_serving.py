@@ -77,7 +77,9 @@ def test_serving_with_deposits_matches_oracle(lib):
     srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=16, streams=2, deposit_every=3,
                      height0=1.2, height_decay=20000.0, amplitude=AMP)
     _register(srv, wk)
-    t, w, step = W.serving_requests(seed=1, n_walkers=N_WALKERS, rate=50_000.0, n_requests=600)
+    # 120 ms of arrivals: walkers go idle between their requests, so they are evicted and
+    # admitted again even if the first launches of the process (code loading) stall the loop
+    t, w, step = W.serving_requests(seed=1, n_walkers=N_WALKERS, rate=5_000.0, n_requests=600)
     print(f"serving replay: {len(t)} requests, {N_WALKERS} walkers, budget {budget} B", flush=True)
     out = srv.replay(w, step, t)
     st = out["stats"]
