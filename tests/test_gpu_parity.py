@@ -799,3 +799,31 @@ def test_c5_grid_sampled(c5):
     hq, dhq, _ = oracle.grid_eval(spec, H, q[:, idx])
     check_bound("C5 grid V", host(V)[idx], hq, ref[2])
     check_bound("C5 grid dV", host(dV)[:, idx], dhq, ref[3])
+
+
+def test_wt_deposit_same_in_every_shape(monkeypatch):
+    """Well-tempered deposits from bias_force (height w0 exp(-V/dT), V the bias
+    the walker saw) land bitwise the same from the fused, split and chained
+    launches."""
+    import dataclasses
+    device()
+    wk = W.ligand_pocket_walkers(seed=81, n_walkers=8, atoms_lo=1000, atoms_hi=2000)
+    spec, hills = W.ligand_pocket_hills(seed=82, n_hills=20000)
+    spec = dataclasses.replace(spec, wt_dT=3.0)
+    got = []
+    for shape in ("fused", "split", "chain"):
+        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+        ctx = make_ctx(spec, hills, capacity=hills.n + wk.nw)
+        first = abp.abp_reserve(ctx, wk.nw)
+        slots = first + np.arange(wk.nw)
+        dw = abp.DeviceWalkers(wk)
+        s, V, dV = abp.bias_force(ctx, dw, deposit_slot=slots, deposit_height=np.full(wk.nw, 0.5))
+        abp.abp_commit(ctx, first + wk.nw)
+        abp.abp_sync(ctx)
+        cen, hts = abp.abp_hills_export(ctx)
+        np.testing.assert_allclose(hts[slots], 0.5 * np.exp(-host(V) / 3.0), rtol=1e-13)
+        np.testing.assert_array_equal(cen[:, slots], host(s))
+        got.append((host(s), host(V), cen[:, slots], hts[slots], host(dw.fx)))
+    for other in got[1:]:
+        for a, b in zip(got[0], other):
+            assert np.array_equal(a, b)
