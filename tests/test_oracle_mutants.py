@@ -40,6 +40,8 @@ MUTANTS = {
     "com_mass_swap": ("grad_a[3 * j + c] = ma[j] / MA * u[c];", "grad_a[3 * j + c] = ma[j] / MB * u[c];"),
     "rmsd_offset": ("sqrt(acc / (double)n + 0.01)", "sqrt(acc / (double)n + 0.1)"),
     "force_sign": ("fx[g] += -dV[a] * grad[a][slot][3 * r + 0];", "fx[g] += dV[a] * grad[a][slot][3 * r + 0];"),
+    "condition_sum_heights": ("nsum_add(&AH, fabs(w * K));", "nsum_add(&AH, fabs(w));"),
+    "condition_sum_gradient": ("nsum_add(&AG[i], fabs(g));", "nsum_add(&AG[i], fabs(w * K));"),
     "neumaier_drop": ("if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;", "if (fabs(a->s) >= fabs(x)) a->c += 0.0;"),
 }
 

@@ -227,6 +227,70 @@ def test_colocated_hills_sum_heights():
 
 
 # --------------------------------------------------------------------------
+# Condition sums A0 = sum |w K| and A_i = sum |w dK/ds_i| (eq. histos taken in
+# absolute value): closed forms for hills away from the query, where K < 1,
+# and a symmetric pair whose gradients cancel while A_i does not.
+# --------------------------------------------------------------------------
+def _kernel_closed(kernel, width, p, delta):
+    """1-D kernel value and derivative d/ds written out from eq. ghill (sigma
+    form) and eq. compacthill, independent of the oracle's kernel routine."""
+    if kernel == W.KERNEL_GAUSS:
+        v = math.exp(-delta * delta / (2.0 * width * width))
+        return v, -delta / (width * width) * v
+    u2 = (delta / width) ** 2
+    if u2 >= 1.0:
+        return 0.0, 0.0
+    v = math.exp(p) * math.exp(-p / (1.0 - u2))
+    return v, -2.0 * p * delta / (width * width * (1.0 - u2) ** 2) * v
+
+
+@pytest.mark.parametrize("kernel", [W.KERNEL_GAUSS, W.KERNEL_COMPACT])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_condition_sums_closed_forms(kernel, ndim):
+    width = ((0.3, 0.25, 0.4) if kernel == W.KERNEL_GAUSS else (0.9, 0.7, 1.1))[:ndim]
+    p = 4
+    spec = W.BiasSpec(ndim=ndim, periodic=(1, 0, 1)[:ndim], lo=(-PI, -2.0, -PI)[:ndim], hi=(PI, 3.0, PI)[:ndim],
+                      width=width, kernel=kernel, p=p)
+    q = np.array([0.2, 0.5, -1.0][:ndim])
+    off = np.array([0.21, -0.17, 0.33][:ndim])          # K < 1 on every axis
+    w = 0.8
+    # one hill off the query: A0 = w K, A_i = |w dK/ds_i|
+    cen = (q - off).reshape(ndim, 1)
+    h, dh, A0, A = oracle.hill_sum(spec, cen, [w], q.reshape(ndim, 1))
+    vals = [_kernel_closed(kernel, width[i], p, off[i]) for i in range(ndim)]
+    K = math.prod(v for v, _ in vals)
+    assert K < 0.9
+    assert h[0] == pytest.approx(w * K, rel=1e-14)
+    assert A0[0] == pytest.approx(w * K, rel=1e-14)
+    for i in range(ndim):
+        g = w * vals[i][1] * math.prod(vals[j][0] for j in range(ndim) if j != i)
+        assert dh[i, 0] == pytest.approx(g, rel=1e-13)
+        assert A[i, 0] == pytest.approx(abs(g), rel=1e-13)
+        assert A[i, 0] != pytest.approx(w * K, rel=1e-3)   # |w dK| differs from |w K| here
+    # two hills at q -+ off: the gradients cancel, A_i is twice one hill's
+    cen = np.hstack([(q - off).reshape(ndim, 1), (q + off).reshape(ndim, 1)])
+    h, dh, A0, A = oracle.hill_sum(spec, cen, [w, w], q.reshape(ndim, 1))
+    assert h[0] == pytest.approx(2 * w * K, rel=1e-14)
+    assert A0[0] == pytest.approx(2 * w * K, rel=1e-14)
+    for i in range(ndim):
+        g = w * vals[i][1] * math.prod(vals[j][0] for j in range(ndim) if j != i)
+        assert abs(dh[i, 0]) <= 1e-14 * abs(g)
+        assert A[i, 0] == pytest.approx(2 * abs(g), rel=1e-13)
+    # unequal heights at unequal distances along axis 0: A0 = sum w_k K_k
+    d2 = off.copy()
+    d2[0] *= 1.7
+    cen = np.hstack([(q - off).reshape(ndim, 1), (q + d2).reshape(ndim, 1)])
+    h, dh, A0, A = oracle.hill_sum(spec, cen, [w, 0.3], q.reshape(ndim, 1))
+    vals2 = [_kernel_closed(kernel, width[i], p, -d2[i]) for i in range(ndim)]
+    K2 = math.prod(v for v, _ in vals2)
+    assert A0[0] == pytest.approx(w * K + 0.3 * K2, rel=1e-14)
+    g1 = w * vals[0][1] * math.prod(vals[j][0] for j in range(1, ndim))
+    g2 = 0.3 * vals2[0][1] * math.prod(vals2[j][0] for j in range(1, ndim))
+    assert dh[0, 0] == pytest.approx(g1 + g2, rel=1e-12, abs=1e-15)
+    assert A[0, 0] == pytest.approx(abs(g1) + abs(g2), rel=1e-13)
+
+
+# --------------------------------------------------------------------------
 # K6: mABP transform (eq. apfm and eq. btraj-grad)
 # --------------------------------------------------------------------------
 def test_mabp_gradient_is_derivative_of_potential():
