@@ -94,7 +94,13 @@ typedef struct {
   int32_t ndim;          /* CV dimension, 1..3 */
   int32_t periodic[3];   /* 1: axis i is periodic on [lo_i, hi_i) with period hi_i - lo_i
                             (minimum-image displacements) */
-  double lo[3], hi[3];   /* non-periodic axes: grid range [lo_i, hi_i], nodes at both ends */
+  double lo[3], hi[3];   /* hi_i > lo_i on every axis. Non-periodic axes: the CV range [lo_i, hi_i]
+                            (the grid's range, nodes at both ends). The FP32 hill sums hold a
+                            non-periodic coordinate as a 32-bit fixed-point offset inside
+                            [lo_i - E_i, hi_i + E_i], E_i = max((hi_i - lo_i)/2, 16 width_i),
+                            in steps of (hi_i - lo_i + 2 E_i)/2^31, and take a value beyond
+                            that window at its edge; the FP64 sums and the history keep
+                            every value as given */
   int32_t kernel;        /* abp_kernel */
   double width[3];       /* Gaussian: sigma_i > 0; compact: a_i > 0 (per-axis a, as the paper allows) */
   int32_t p;             /* compact kernel exponent, 1..64 (ignored for Gaussian) */

@@ -10,10 +10,11 @@ namespace abp {
 constexpr float kTinyGap = 0x1p-40f;   // floor of 1 - (delta/a)^2 in the FP32 compact kernel
 
 // ---------------------------------------------------------------------------
-// Working form of one CV coordinate (FP32 path).
-// Periodic axis: 32-bit fixed-point fraction of the period, so the unsigned
-// difference of two words is the minimum-image displacement mod 2^32.
-// Non-periodic axis: the bits of the FP32 value.
+// Working form of one CV coordinate (FP32 path): a 32-bit fixed-point word.
+// Periodic axis: fraction of the period, so the unsigned difference of two
+// words is the minimum-image displacement mod 2^32. Non-periodic axis: signed
+// offset from the window's middle, clamped to +-kFixLimit (the window's edge),
+// so the difference of two words never wraps.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t work32(const Consts& K, int axis, double s) {
   if (K.periodic[axis]) {
@@ -21,7 +22,8 @@ __device__ __forceinline__ uint32_t work32(const Consts& K, int axis, double s) 
     t -= floor(t);
     return (uint32_t)(uint64_t)rint(t * 4294967296.0);
   }
-  return __float_as_uint((float)s);
+  const double t = rint((s - K.fix_mid[axis]) * K.fix_scale[axis]);
+  return (uint32_t)(int32_t)fmin(fmax(t, -kFixLimit), kFixLimit);
 }
 
 // Working form in the FP64 path: turns on periodic axes (wrapped later).
@@ -58,7 +60,8 @@ __device__ __forceinline__ uint32_t rec_word(const int4& h, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// One hill against one query, FP32. P[0] += w K; P[1+i] += w K * f_i where
+// One hill against one query, FP32 (both working forms are fixed point, so
+// PMASK does not change the arithmetic). P[0] += w K; P[1+i] += w K * f_i where
 // f_i is the working displacement (Gaussian) or u/(1-u^2)^2 (compact); the
 // epilogue multiplies by the per-axis gradient scale. The height enters as
 // log2(w) in the exponent, so w K costs no separate multiply.
@@ -72,13 +75,7 @@ __device__ __forceinline__ void pair32(const uint32_t (&qw)[D], const int4& h, c
   float a = __int_as_float(h.w);
   float d[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const uint32_t hc = rec_word(h, i);
-    if ((PMASK >> i) & 1)
-      d[i] = (float)(int32_t)(qw[i] - hc);
-    else
-      d[i] = __uint_as_float(qw[i]) - __uint_as_float(hc);
-  }
+  for (int i = 0; i < D; ++i) d[i] = (float)(int32_t)(qw[i] - rec_word(h, i));   // exact integer difference
   float f[D];
   if (KERN == ABP_K_GAUSS) {
     if (ISO) {

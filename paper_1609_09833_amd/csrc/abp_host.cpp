@@ -3,6 +3,7 @@
 // the device memory of a context, and enqueues the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,7 +107,7 @@ abp_status check_desc(const abp_bias_desc* d) {
     if (d->periodic[i] != 0 && d->periodic[i] != 1) return fail(ABP_E_INVAL, "periodic[%d] must be 0 or 1", i);
     if (!finite_pos(d->width[i])) return fail(ABP_E_INVAL, "width[%d] must be > 0", i);
     if (!std::isfinite(d->lo[i]) || !std::isfinite(d->hi[i])) return fail(ABP_E_INVAL, "lo/hi[%d] not finite", i);
-    if ((d->periodic[i] || any_grid) && !(d->hi[i] > d->lo[i])) return fail(ABP_E_INVAL, "axis %d needs hi > lo", i);
+    if (!(d->hi[i] > d->lo[i])) return fail(ABP_E_INVAL, "axis %d needs hi > lo", i);
     if (any_grid && (d->grid_n[i] < 2 || d->grid_n[i] > (1 << 20)))
       return fail(ABP_E_INVAL, "grid_n[%d] must be 2..2^20 when a grid is requested", i);
   }
@@ -145,7 +146,13 @@ void make_consts(const abp_bias_desc& d, Consts& K) {
       K.period[i] = L;
       K.inv_period[i] = 1.0 / L;
     }
-    const double unit32 = per ? L / kTwo32 : 1.0;   // working displacement units, FP32 path
+    // FP32 working words (see Consts): the period in 2^32 steps, or the
+    // half-width of the window [lo - E, hi + E] in 2^30 steps
+    const double reach = std::max(0.5 * L, 16.0 * d.width[i]);
+    const double half = 0.5 * L + reach;
+    const double unit32 = per ? L / kTwo32 : half / 1073741824.0;
+    K.fix_mid[i] = per ? 0.0 : 0.5 * (d.lo[i] + d.hi[i]);
+    K.fix_scale[i] = per ? 0.0 : 1.0 / unit32;
     const double unit64 = per ? L : 1.0;            // FP64 path (turns)
     K.per64[i] = per ? 1.0 : 0.0;
     const double wdt = d.width[i];

@@ -22,6 +22,9 @@ constexpr int kTile64 = 512;     // hills per LDS tile in the FP64 direct sum (1
 constexpr int kChunk = ABP_CHUNK; // hills summed plainly before each compensated (Kahan) step
 constexpr int kQ2D = ABP_Q2D;     // queries per thread in the 2-D/3-D FP32 direct sum
 
+// Largest magnitude of a non-periodic FP32 working word (see Consts).
+constexpr double kFixLimit = 1073741823.0;   // 2^30 - 1
+
 // log2 of a zero height in the FP64 sums: finite, so that the exponent of a
 // term stays finite, and far enough below -1074 that the term is exactly 0.
 constexpr double kLog2Zero = -2048.0;
@@ -31,17 +34,23 @@ enum : int32_t { kErrIndex = 1 << 0, kErrNonfinite = 1 << 1, kErrInval = 1 << 2 
 
 // Per-context constants, computed once on the host from abp_bias_desc.
 //
-// Working displacements: in the FP32 path a periodic coordinate is held as a
-// 32-bit fixed-point fraction of its period, so the difference of two such
-// words (mod 2^32) is already the minimum image; converted to float it is a
-// displacement in units of L/2^32. A non-periodic coordinate is a float in
-// its own units. In the FP64 path periodic coordinates are fractions of the
-// period (turns) wrapped with rint; non-periodic ones are raw.
+// Working displacements: in the FP32 path every coordinate is a 32-bit
+// fixed-point word, so a displacement is an integer difference, converted to
+// float in units of unit32 (its error does not grow with the coordinate's
+// magnitude). A periodic coordinate is a fraction of its period (unit
+// L/2^32), so the difference of two words (mod 2^32) is already the minimum
+// image. A non-periodic coordinate is a signed offset from the middle of the
+// window [lo - E, hi + E], E = max((hi - lo)/2, 16 width), in units of the
+// window's half-width / 2^30; values beyond the window are taken at its edge.
+// Words then stay within +-(2^30 - 1), so a difference never wraps. In the
+// FP64 path periodic coordinates are fractions of the period (turns) wrapped
+// with rint; non-periodic ones are raw.
 struct Consts {
   int32_t ndim, kernel, p, transform;
   int32_t quant;                   // 1: evaluate and deposit at the nearest grid node
   int32_t periodic[3];
   double lo[3], hi[3], period[3], inv_period[3];
+  double fix_mid[3], fix_scale[3]; // non-periodic FP32 words: rint((x - fix_mid) * fix_scale)
   // FP32 path, per axis: Gaussian exponent factor on the working displacement
   // (log2(e) unit^2 / (2 sigma^2)), compact scale (unit / a), gradient scale.
   float kf32[3], ua32[3];

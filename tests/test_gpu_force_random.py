@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_1609_09833_amd import workloads as W
 from tests.gpu_common import cv_atom_grad_abs, device, host, to_dev
-from tests.tolerance import check_bound, fp32_floor, rounding_error_scales
+from tests.tolerance import check_bound, fp32_floor, rounding_error_scales, working_coord_error
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -147,7 +147,7 @@ def test_random_bias_force(seed, monkeypatch):
         unit = 2.0 ** -53 if fp64 else 2.0 ** -24
         h, dh = oracle.hill_sum(spec, hills.centers, hills.heights, so)[:2]
         slope = oracle.transform(spec, h, dh)[2]
-        E0, E = rounding_error_scales(spec, hills.centers, hills.heights, so, unit, unit)
+        E0, E = rounding_error_scales(spec, hills.centers, hills.heights, so, unit, working_coord_error(spec, fp64))
         E0, E = slope * E0, slope[None, :] * E
     check_bound("V", host(V), ref[1], sV, tol, fl + E0)
     check_bound("dV/ds", host(dV), ref[2], sG, tol, gfl + E)

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_1609_09833_amd import workloads as W
 from tests.gpu_common import device, to_dev, host
-from tests.tolerance import check_bound, fp32_floor, rounding_error_scales
+from tests.tolerance import check_bound, fp32_floor, rounding_error_scales, working_coord_error
 
 pytestmark = pytest.mark.gpu
 PI = math.pi
@@ -79,7 +79,7 @@ def test_random_spec_parity(seed):
         gfl = fl * 1e4 * max(1.0, max(1.0 / w ** 2 for w in spec.width))
         snap = (lambda i, x: oracle.snap(spec, i, x)) if spec.quantize else None
         E0, E = rounding_error_scales(spec, hills.centers, hills.heights, qq, 2.0 ** -53 if fp64 else 2.0 ** -24,
-                                      2.0 ** -53 if fp64 else 2.0 ** -24, snap=snap)
+                                      working_coord_error(spec, fp64), snap=snap)
         got_V, got_dV = host(V), host(dV)
         check_bound(f"seed {seed} prec {prec} V", got_V, Vo, sV, tol, fl + slope * E0)
         check_bound(f"seed {seed} prec {prec} dV", got_dV, dVo, sG, tol, gfl + slope[None, :] * E)
