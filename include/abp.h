@@ -51,7 +51,8 @@ typedef enum {
   ABP_E_CAPACITY = 3,    /* the history would exceed its capacity */
   ABP_E_DEVICE = 4,      /* a HIP runtime call failed */
   ABP_E_INDEX = 5,       /* device-detected: atom index out of range or list not valid */
-  ABP_E_NONFINITE = 6    /* device-detected: non-finite position/mass/height, or negative height */
+  ABP_E_NONFINITE = 6,   /* device-detected: non-finite position/mass/height, or negative height */
+  ABP_E_BUSY = 7         /* the server holds as many requests as it can stage; poll, then retry */
 } abp_status;
 
 typedef enum { ABP_F32 = 0, ABP_F64 = 1 } abp_dtype;
@@ -226,8 +227,7 @@ abp_status cv_compute(abp_ctx* ctx, const abp_cv_desc* cv, const abp_walkers* wa
  * Launches: one for the grid form and for histories of up to 16,384 hills;
  * for longer ones three (CV, hill sum, finish) or, for one or two walkers,
  * one chained launch; both use a workspace the context allocates and clears
- * on first need (the environment variable ABP_FORCE_SHAPE=fused|split|chain
- * forces one shape, chain for up to 64 walkers). A walker's result is
+ * on first need (abp_set_force_shape fixes the shape). A walker's result is
  * bitwise the same in any batch and any shape. Once the workspace exists the
  * call enqueues kernels only, so it can be captured in a HIP graph. Calls
  * that share a context's workspace must not run concurrently on different
@@ -236,6 +236,20 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
                       const abp_walkers* walkers, const int64_t* n_visible,
                       const int64_t* deposit_slot, const double* deposit_height,
                       double* s, double* V, double* dVds, abp_stream stream);
+
+/* Launch shapes of bias_force's direct sum (see bias_force). */
+typedef enum {
+  ABP_SHAPE_AUTO = 0,    /* fused up to 16,384 hills; then chained for 1-2 walkers, else split */
+  ABP_SHAPE_FUSED = 1,   /* one launch, one block per walker sums every hill */
+  ABP_SHAPE_SPLIT = 2,   /* CV, hill-sum and finish launches */
+  ABP_SHAPE_CHAIN = 3    /* one launch of several blocks per walker (batches of up to 64 walkers;
+                            larger batches take SPLIT) */
+} abp_force_shape;
+
+/* Fix the launch shape of later bias_force calls on the context (AUTO by
+ * default). Every shape gives bitwise the same results; a fixed shape serves
+ * timing and tests that compare the shapes. ABP_E_INVAL for an unknown shape. */
+abp_status abp_set_force_shape(abp_ctx* ctx, int32_t shape);
 
 /* Reserve n history slots after every slot reserved so far (host-side
  * bookkeeping, nothing enqueued). *first receives the first slot index.
@@ -265,42 +279,54 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
 
 /* ---- Serving loop -------------------------------------------------------
  * Continuous batching of bias-force requests from many walkers (MD replicas)
- * that share the context's hill history. Not in the paper (one walker per MD
- * engine there); it serves the same per-step problem to many engines at once.
+ * that share the context's hill history. The paper runs one walker per MD
+ * engine; the request is its per-step exchange (section "Minimization of
+ * Interprocess Communications"): a walker's engine sends the coordinates of
+ * its CV atoms for one MD step and gets back the bias force on exactly those
+ * atoms, which it adds to its own forces, together with s, V and dV/ds.
  *
- * Each walker's engine state (base and current positions, masses and forces
- * of all its atoms, ABP_SERVER_BYTES_PER_ATOM bytes per atom) lives in device
- * memory while the walker is admitted; admission copies the base positions
- * and masses of the walker's CV atoms from host memory, the only atoms the
- * bias path reads.
- * Walkers are admitted first come first served against an HBM budget; when
- * memory is short the least recently used idle walker is evicted. A request
- * (walker, step) is evaluated against the hills committed when its batch is
- * formed (its version). A request whose step is a positive multiple of
- * deposit_every deposits a hill at its CV value into a history slot reserved
- * in batch-formation order; slots are committed once every earlier slot is
- * done. A walker has at most one request in flight; up to `streams` batches
- * run at once, each formed from whatever requests are ready when a stream
- * frees up. Positions for a step come from a synthetic engine step on the
- * device: base positions plus amplitude * u, u in [-1, 1) hashed from
- * (walker, step, atom, coordinate). The bias path itself is bias_force's. */
+ * Life cycle: abp_server_create, abp_server_add_walker for every walker,
+ * abp_server_start (ends registration, starts the scheduler thread), then any
+ * number of abp_server_submit / abp_server_poll calls from any host threads,
+ * abp_server_stop (finishes every submitted request), abp_server_destroy.
+ * Between start and stop the server owns the context: make no other call on
+ * it (its history grows by the requests' deposits).
+ *
+ * A walker's CV atoms are the distinct atoms of its CV lists, in increasing
+ * index order (abp_server_walker_atoms); positions are submitted and forces
+ * returned in that order. While a walker is resident its device state is
+ * ABP_SERVER_BYTES_PER_ATOM bytes per CV atom (positions, masses, forces);
+ * walkers are admitted first come first served against the HBM budget, and
+ * the least recently used idle walker is evicted when memory is short
+ * (admission copies its CV-atom masses to the device once). A walker has at
+ * most one request in the device at a time, and its requests run in
+ * submission order. A batch is formed from the resident walkers with a
+ * request whenever one of `streams` batch slots is free; up to `streams`
+ * batches are in flight. Every request of a batch sees the hills committed
+ * when the batch was formed (its version). A request whose step is a positive
+ * multiple of deposit_every deposits a hill at its CV value (height
+ * height0 * exp(-k / height_decay) for history slot k) into a slot reserved
+ * in batch-formation order; slots are committed, in order, once every earlier
+ * slot is done. A request's result is bitwise the same whatever batch it
+ * runs in. Forces are FP32; s, V and dV/ds FP64. */
 typedef struct abp_server abp_server;
 
-#define ABP_SERVER_BYTES_PER_ATOM 40  /* ten FP32 arrays: x0, y0, z0, x, y, z, mass, fx, fy, fz */
+#define ABP_SERVER_BYTES_PER_ATOM 28  /* seven FP32 device arrays per CV atom: x, y, z, mass, fx, fy, fz */
 
 typedef struct {
-  int64_t hbm_budget_bytes;  /* device memory for walker engine state (ABP_SERVER_BYTES_PER_ATOM per atom) */
-  int32_t max_batch;         /* requests per batch, >= 1 (1 = one launch per request) */
+  int64_t hbm_budget_bytes;  /* device memory for resident walker state (ABP_SERVER_BYTES_PER_ATOM per CV atom) */
+  int32_t max_batch;         /* requests per batch, 1..65536 (1 = one launch per request) */
   int32_t streams;           /* batches in flight, 1..8 */
   int32_t deposit_every;     /* deposit period in steps; 0: never */
-  int32_t prec;              /* abp_prec of the hill sum */
+  int32_t prec;              /* abp_prec of the hill sum (DIRECT evaluation) */
   double height0;            /* deposit height height0 * exp(-k / height_decay) for slot k */
   double height_decay;       /* 0: constant height0 */
-  float amplitude;           /* synthetic engine displacement bound, nm (power of two: exact) */
   int32_t cv_kind[3];        /* abp_cv_kind of CV a (a < ndim), same rules as abp_cv_desc.kind */
+  int32_t max_pending;       /* requests submitted and not yet polled, >= 1 (bounds host staging) */
 } abp_server_desc;
 
 typedef struct {
+  int64_t submitted;         /* requests accepted since start */
   int64_t completed;         /* requests done */
   int64_t batches;           /* launches of the bias-force path */
   int64_t max_batch_seen;
@@ -308,43 +334,101 @@ typedef struct {
   int64_t evictions;
   int64_t deposits;          /* hills committed by requests */
   int64_t peak_resident;     /* most walkers resident at once */
-  int64_t pool_atoms;        /* atoms the budget holds */
-  double wall_seconds;       /* replay wall time */
+  int64_t pool_atoms;        /* CV atoms the budget holds */
+  double wall_seconds;       /* from start to stop (or to now while running) */
 } abp_server_stats;
 
-/* Create a server on a context (DIRECT sums only). ABP_E_INVAL for a bad
- * descriptor, ABP_E_NOMEM if the budget or the per-batch buffers cannot be
- * allocated. */
+/* One completed request (abp_server_poll). Times are seconds on the server's
+ * steady clock, counted from abp_server_create. */
+typedef struct {
+  int64_t request;           /* id returned by abp_server_submit */
+  int64_t step;
+  int64_t version;           /* hills visible to the request */
+  int64_t deposit_slot;      /* history slot it deposited into, or -1 */
+  int32_t walker;
+  int32_t n_cv_atoms;        /* forces written to the request's force_out */
+  double t_submit;           /* when abp_server_submit accepted it */
+  double t_done;             /* when the scheduler saw its batch complete */
+  double s[3];               /* CVs (entries >= ncv unused) */
+  double V;
+  double dVds[3];
+} abp_server_result;
+
+/* One batch (abp_server_trace), times as in abp_server_result. */
+typedef struct {
+  double t_formed;           /* the scheduler took its requests */
+  double t_launched;         /* all of its work was enqueued */
+  double t_done;             /* the scheduler saw it complete */
+  int64_t requests;
+  int64_t version;
+  int32_t slot;              /* batch slot (stream) it ran on */
+  int32_t admitted;          /* walkers admitted for it (their masses went with it) */
+} abp_server_batch;
+
+/* Create a server on a context (DIRECT sums only). Allocates the walker pool
+ * (the budget), per-slot batch buffers sized for max_batch requests at the
+ * history's capacity, and pinned host staging for max_pending requests once
+ * the walkers are known (abp_server_start). ABP_E_INVAL for a bad descriptor,
+ * ABP_E_NOMEM if memory cannot be allocated. */
 abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_server** out);
 
-/* Wait for outstanding work and free the server (not the context). */
+/* Stop the scheduler if it runs (as abp_server_stop) and free the server (not
+ * the context). Results not polled are dropped. */
 abp_status abp_server_destroy(abp_server* srv);
 
-/* Register a walker (HOST arrays): n_atoms base positions x0/y0/z0 and
- * masses, of which the server keeps a copy for the CV atoms (the only atoms
- * it touches); list_len[2*ncv] lengths of the CV lists (CV a, slot t at
- * 2a+t, rules as in abp_cv_desc) and list_idx their concatenation in that
- * order; ref_x/y/z aligned with list_idx (NULL when no CV is RMSD_OFF).
- * Lists are checked here (ABP_E_INVAL); a walker whose state exceeds the
- * whole budget is refused with ABP_E_NOMEM. *walker_id receives its id. */
-abp_status abp_server_add_walker(abp_server* srv, int32_t n_atoms, const float* x0, const float* y0,
-                                 const float* z0, const float* mass, const int32_t* list_len,
+/* Register a walker (HOST arrays, copied): n_atoms atoms with masses
+ * mass[n_atoms] (of which the server keeps those of the CV atoms);
+ * list_len[2*ncv] lengths of the CV lists (CV a, slot t at 2a+t, rules as in
+ * abp_cv_desc) and list_idx their concatenation in that order, walker-local
+ * indices; ref_x/y/z aligned with list_idx (NULL when no CV is RMSD_OFF).
+ * Lists and masses are checked here (ABP_E_INVAL); a walker whose CV atoms
+ * exceed the whole budget is refused with ABP_E_NOMEM. Only before
+ * abp_server_start. *walker_id receives its id (0, 1, ... in call order) and
+ * *n_cv_atoms (may be NULL) the number of its CV atoms. */
+abp_status abp_server_add_walker(abp_server* srv, int32_t n_atoms, const float* mass, const int32_t* list_len,
                                  const int32_t* list_idx, const float* ref_x, const float* ref_y,
-                                 const float* ref_z, int32_t* walker_id);
+                                 const float* ref_z, int32_t* walker_id, int32_t* n_cv_atoms);
 
-/* Replay an open-loop schedule of n requests (HOST arrays): walker[i] at
- * step[i] arrives t_arrival[i] seconds after the call starts (sorted,
- * non-decreasing); a walker's steps must increase. Blocks until every request
- * is done. Outputs (HOST arrays, each may be NULL): t_done[i] seconds when
- * completion was observed; version[i] hills visible to the request;
- * deposit_slot[i] history slot it deposited into or -1; s[ncv][n], V[n],
- * dVds[ncv][n]. */
-abp_status abp_server_replay(abp_server* srv, int64_t n, const int32_t* walker, const int64_t* step,
-                             const double* t_arrival, double* t_done, int64_t* version, int64_t* deposit_slot,
-                             double* s, double* V, double* dVds);
+/* The CV atoms of a walker (walker-local indices, increasing) into the HOST
+ * array idx (may be NULL); *n receives their number. */
+abp_status abp_server_walker_atoms(abp_server* srv, int32_t walker, int32_t* idx, int32_t* n);
 
-/* Counters of the last replay. */
+/* End registration, copy the CV lists to the device, warm up every kernel a
+ * batch can launch (one batch of each launch shape, no deposit, results
+ * discarded) and start the scheduler thread. Statistics and the batch trace
+ * restart, and results of an earlier run not yet polled are dropped. The
+ * context must have no reserved, uncommitted slots. */
+abp_status abp_server_start(abp_server* srv);
+
+/* Submit one request: walker's positions at MD step `step`, HOST array
+ * xyz[3][n_cv] (x of every CV atom, then y, then z, in abp_server_walker_atoms
+ * order), copied before the call returns. force_out (HOST, [3][n_cv] in the
+ * same layout, or NULL) receives the bias force on those atoms when the
+ * request is polled; it must stay valid until then. Non-finite coordinates
+ * are refused (ABP_E_NONFINITE). ABP_E_BUSY when max_pending requests are
+ * submitted and not yet polled (poll, then submit again). *request_id (may be
+ * NULL) receives the request's id (0, 1, ... in acceptance order). Thread-safe. */
+abp_status abp_server_submit(abp_server* srv, int32_t walker, int64_t step, const float* xyz, float* force_out,
+                             int64_t* request_id);
+
+/* Take up to max completed requests (in completion order) into out[] and
+ * write their forces to their force_out arrays; *n receives the number taken.
+ * Waits up to wait_us microseconds for a first result when none is ready
+ * (0: do not wait). Thread-safe. */
+abp_status abp_server_poll(abp_server* srv, abp_server_result* out, int64_t max, int64_t* n, int64_t wait_us);
+
+/* Wait until every submitted request is done, then stop the scheduler thread.
+ * Completed requests stay available to abp_server_poll. Device-detected
+ * errors of the run are returned here (as abp_sync). */
+abp_status abp_server_stop(abp_server* srv);
+
+/* Counters since the last start. */
 abp_status abp_server_get_stats(abp_server* srv, abp_server_stats* out);
+
+/* Copy up to max batch records (the most recent ones, oldest first) of the
+ * run since the last start into out; *n receives the number copied. The
+ * server keeps the last 2^20 batches. */
+abp_status abp_server_trace(abp_server* srv, abp_server_batch* out, int64_t max, int64_t* n);
 
 /* Static message for a status code. */
 const char* abp_status_str(abp_status status);

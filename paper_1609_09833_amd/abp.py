@@ -16,20 +16,21 @@ import torch  # loaded first so that libabp.so binds to the same HIP runtime as 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ABP_LIB_PATH") or os.path.join(_PKG, "libabp.so")
 
-ABP_OK, ABP_E_INVAL, ABP_E_NOMEM, ABP_E_CAPACITY, ABP_E_DEVICE, ABP_E_INDEX, ABP_E_NONFINITE = range(7)
+ABP_OK, ABP_E_INVAL, ABP_E_NOMEM, ABP_E_CAPACITY, ABP_E_DEVICE, ABP_E_INDEX, ABP_E_NONFINITE, ABP_E_BUSY = range(8)
 ABP_F32, ABP_F64 = 0, 1
 ABP_PREC_FP32_KAHAN, ABP_PREC_FP32_NAIVE, ABP_PREC_FP64 = 0, 1, 2
 ABP_K_GAUSS, ABP_K_COMPACT = 0, 1
 ABP_T_PLAIN, ABP_T_MABP = 0, 1
 ABP_EVAL_DIRECT, ABP_EVAL_GRID = 0, 1
 ABP_CV_COM_DIST, ABP_CV_TORSION, ABP_CV_RMSD_OFF = 0, 1, 2
-ABP_SERVER_BYTES_PER_ATOM = 40          # device pool bytes per walker atom
+ABP_SERVER_BYTES_PER_ATOM = 28          # device pool bytes per CV atom of a resident walker
 
 EXPORTED = ("abp_create", "abp_destroy", "bias_deposit", "bias_eval", "cv_compute", "bias_force",
-            "abp_reserve", "abp_commit", "abp_sync", "abp_num_hills", "abp_hills_export",
+            "abp_set_force_shape", "abp_reserve", "abp_commit", "abp_sync", "abp_num_hills", "abp_hills_export",
             "abp_grid_export", "abp_status_str", "abp_last_error",
-            "abp_server_create", "abp_server_destroy", "abp_server_add_walker", "abp_server_replay",
-            "abp_server_get_stats")
+            "abp_server_create", "abp_server_destroy", "abp_server_add_walker", "abp_server_walker_atoms",
+            "abp_server_start", "abp_server_submit", "abp_server_poll", "abp_server_stop",
+            "abp_server_get_stats", "abp_server_trace")
 
 
 class AbpError(RuntimeError):
@@ -62,13 +63,28 @@ class WalkersDesc(C.Structure):
 class ServerDesc(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32),
                 ("deposit_every", C.c_int32), ("prec", C.c_int32), ("height0", C.c_double),
-                ("height_decay", C.c_double), ("amplitude", C.c_float), ("cv_kind", C.c_int32 * 3)]
+                ("height_decay", C.c_double), ("cv_kind", C.c_int32 * 3), ("max_pending", C.c_int32)]
 
 
 class ServerStats(C.Structure):
-    _fields_ = [("completed", C.c_int64), ("batches", C.c_int64), ("max_batch_seen", C.c_int64),
-                ("admissions", C.c_int64), ("evictions", C.c_int64), ("deposits", C.c_int64),
-                ("peak_resident", C.c_int64), ("pool_atoms", C.c_int64), ("wall_seconds", C.c_double)]
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("max_batch_seen", C.c_int64), ("admissions", C.c_int64), ("evictions", C.c_int64),
+                ("deposits", C.c_int64), ("peak_resident", C.c_int64), ("pool_atoms", C.c_int64),
+                ("wall_seconds", C.c_double)]
+
+
+# abp_server_result and abp_server_batch as numpy record types (same layout)
+def _np_types():
+    import numpy as np
+    result = np.dtype([("request", "<i8"), ("step", "<i8"), ("version", "<i8"), ("deposit_slot", "<i8"),
+                       ("walker", "<i4"), ("n_cv_atoms", "<i4"), ("t_submit", "<f8"), ("t_done", "<f8"),
+                       ("s", "<f8", (3,)), ("V", "<f8"), ("dVds", "<f8", (3,))])
+    batch = np.dtype([("t_formed", "<f8"), ("t_launched", "<f8"), ("t_done", "<f8"), ("requests", "<i8"),
+                      ("version", "<i8"), ("slot", "<i4"), ("admitted", "<i4")])
+    return result, batch
+
+
+SERVER_RESULT, SERVER_BATCH = _np_types()
 
 
 def _load():
@@ -91,11 +107,17 @@ def _load():
         "abp_grid_export": ([P, P, i64], i32),
         "abp_status_str": ([i32], C.c_char_p),
         "abp_last_error": ([], C.c_char_p),
+        "abp_set_force_shape": ([P, i32], i32),
         "abp_server_create": ([P, P, P], i32),
         "abp_server_destroy": ([P], i32),
-        "abp_server_add_walker": ([P, i32, P, P, P, P, P, P, P, P, P, P], i32),
-        "abp_server_replay": ([P, i64, P, P, P, P, P, P, P, P, P], i32),
+        "abp_server_add_walker": ([P, i32, P, P, P, P, P, P, P, P], i32),
+        "abp_server_walker_atoms": ([P, i32, P, P], i32),
+        "abp_server_start": ([P], i32),
+        "abp_server_submit": ([P, i32, i64, P, P, P], i32),
+        "abp_server_poll": ([P, P, i64, P, i64], i32),
+        "abp_server_stop": ([P], i32),
         "abp_server_get_stats": ([P, P], i32),
+        "abp_server_trace": ([P, P, i64, P], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -293,6 +315,14 @@ def bias_force(ctx, walkers, mode=ABP_EVAL_DIRECT, prec=ABP_PREC_FP32_KAHAN, n_v
     return s, V, dVds
 
 
+SHAPES = {"auto": 0, "fused": 1, "split": 2, "chain": 3}
+
+
+def abp_set_force_shape(ctx, shape):
+    """Fix bias_force's launch shape on ctx: "auto", "fused", "split" or "chain"."""
+    _check(lib.abp_set_force_shape(ctx.handle, SHAPES[shape] if isinstance(shape, str) else int(shape)))
+
+
 def abp_reserve(ctx, n):
     first = C.c_int64()
     _check(lib.abp_reserve(ctx.handle, int(n), C.byref(first)))
@@ -336,19 +366,23 @@ def abp_grid_export(ctx):
 
 class Server:
     """An abp_server: continuous batching of bias-force requests from many
-    walkers over one context's hill history (HOST-side inputs and outputs)."""
+    walkers over one context's hill history. Requests carry the positions of
+    a walker's CV atoms (HOST numpy arrays [3][n_cv]) and return the bias
+    force on them."""
 
     def __init__(self, ctx, kinds, hbm_budget_bytes=1 << 30, max_batch=1024, streams=2, deposit_every=0,
-                 prec=ABP_PREC_FP32_KAHAN, height0=0.0, height_decay=0.0, amplitude=0.0078125):
+                 prec=ABP_PREC_FP32_KAHAN, height0=0.0, height_decay=0.0, max_pending=4096):
         self.ctx = ctx
         d = ServerDesc()
         d.hbm_budget_bytes, d.max_batch, d.streams = int(hbm_budget_bytes), int(max_batch), int(streams)
         d.deposit_every, d.prec = int(deposit_every), int(prec)
-        d.height0, d.height_decay, d.amplitude = float(height0), float(height_decay), float(amplitude)
+        d.height0, d.height_decay, d.max_pending = float(height0), float(height_decay), int(max_pending)
         for i in range(3):
             d.cv_kind[i] = int(kinds[i]) if i < len(kinds) else 0
         self.desc = d
         self.ncv = ctx.ndim
+        self._outs = {}                 # request id -> force_out array, alive until polled
+        self._ncv_atoms = []
         h = C.c_void_p()
         _check(lib.abp_server_create(ctx.handle, C.byref(d), C.byref(h)))
         self.handle = h
@@ -357,6 +391,7 @@ class Server:
         if getattr(self, "handle", None):
             _check(lib.abp_server_destroy(self.handle))
             self.handle = None
+            self._outs.clear()
 
     def __del__(self):
         try:
@@ -364,49 +399,78 @@ class Server:
         except Exception:
             pass
 
-    def add_walker(self, x0, y0, z0, mass, list_len, list_idx, ref_x=None, ref_y=None, ref_z=None):
+    def add_walker(self, mass, list_len, list_idx, ref_x=None, ref_y=None, ref_z=None):
+        """Register a walker (all its atoms' masses, CV lists of walker-local
+        indices); returns (walker id, number of its CV atoms)."""
         import numpy as np
         f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
-        x0, y0, z0, mass = f32(x0), f32(y0), f32(z0), f32(mass)
+        mass = f32(mass)
         ll = np.ascontiguousarray(list_len, dtype=np.int32)
         li = np.ascontiguousarray(list_idx, dtype=np.int32)
         if ll.shape != (2 * self.ncv,):
             raise ValueError("list_len must hold 2*ncv lengths")
         refs = [None if r is None else f32(r) for r in (ref_x, ref_y, ref_z)]
         p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
-        wid = C.c_int32()
-        _check(lib.abp_server_add_walker(self.handle, int(x0.shape[0]), p(x0), p(y0), p(z0), p(mass), p(ll),
+        wid, ncv = C.c_int32(), C.c_int32()
+        _check(lib.abp_server_add_walker(self.handle, int(mass.shape[0]), p(mass), p(ll),
                                          p(li if li.size else np.zeros(1, np.int32)), p(refs[0]), p(refs[1]),
-                                         p(refs[2]), C.byref(wid)))
-        return wid.value
+                                         p(refs[2]), C.byref(wid), C.byref(ncv)))
+        self._ncv_atoms.append(ncv.value)
+        return wid.value, ncv.value
 
-    def replay(self, walker, step, t_arrival):
-        """Run an open-loop schedule; returns a dict of per-request numpy arrays
-        (t_done, version, deposit_slot, s[ncv][n], V, dVds[ncv][n]) and stats."""
+    def walker_atoms(self, walker):
+        """The walker's CV atoms (walker-local indices, increasing): the order of
+        submitted positions and returned forces."""
         import numpy as np
-        w = np.ascontiguousarray(walker, dtype=np.int32)
-        st = np.ascontiguousarray(step, dtype=np.int64)
-        ta = np.ascontiguousarray(t_arrival, dtype=np.float64)
-        n = int(w.shape[0])
-        m = max(n, 1)
-        out = {
-            "t_done": np.full(m, np.nan), "version": np.full(m, -1, np.int64),
-            "deposit_slot": np.full(m, -2, np.int64), "s": np.full((self.ncv, m), np.nan),
-            "V": np.full(m, np.nan), "dVds": np.full((self.ncv, m), np.nan),
-        }
-        p = lambda a: a.ctypes.data_as(C.c_void_p)
-        s_buf = np.full(self.ncv * m, np.nan)
-        d_buf = np.full(self.ncv * m, np.nan)
-        _check(lib.abp_server_replay(self.handle, n, p(w), p(st), p(ta), p(out["t_done"]), p(out["version"]),
-                                     p(out["deposit_slot"]), p(s_buf), p(out["V"]), p(d_buf)))
-        out["s"] = s_buf[: self.ncv * n].reshape(self.ncv, n)
-        out["dVds"] = d_buf[: self.ncv * n].reshape(self.ncv, n)
-        for k in ("t_done", "version", "deposit_slot", "V"):
-            out[k] = out[k][:n]
-        out["stats"] = self.stats()
+        n = C.c_int32()
+        _check(lib.abp_server_walker_atoms(self.handle, int(walker), None, C.byref(n)))
+        idx = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(lib.abp_server_walker_atoms(self.handle, int(walker), idx.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return idx[: n.value]
+
+    def start(self):
+        _check(lib.abp_server_start(self.handle))
+
+    def stop(self):
+        _check(lib.abp_server_stop(self.handle))
+
+    def submit(self, walker, step, xyz, force_out=None):
+        """Submit positions xyz (float32 [3][n_cv]); force_out (float32 [3][n_cv],
+        C-contiguous) receives the forces when the request is polled."""
+        import numpy as np
+        xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+        if force_out is not None and (force_out.dtype != np.float32 or not force_out.flags.c_contiguous
+                                      or force_out.size < xyz.size):
+            raise ValueError("force_out must be a C-contiguous float32 array as large as xyz")
+        rid = C.c_int64()
+        _check(lib.abp_server_submit(self.handle, int(walker), int(step), xyz.ctypes.data_as(C.c_void_p),
+                                     None if force_out is None else force_out.ctypes.data_as(C.c_void_p),
+                                     C.byref(rid)))
+        if force_out is not None:
+            self._outs[rid.value] = force_out
+        return rid.value
+
+    def poll(self, max_results=4096, wait_us=0):
+        """Completed requests as a numpy record array (SERVER_RESULT fields)."""
+        import numpy as np
+        out = np.zeros(max(int(max_results), 1), dtype=SERVER_RESULT)
+        n = C.c_int64()
+        _check(lib.abp_server_poll(self.handle, out.ctypes.data_as(C.c_void_p), int(max_results), C.byref(n),
+                                   int(wait_us)))
+        out = out[: n.value]
+        for r in out["request"]:
+            self._outs.pop(int(r), None)
         return out
 
     def stats(self):
         s = ServerStats()
         _check(lib.abp_server_get_stats(self.handle, C.byref(s)))
         return {name: getattr(s, name) for name, _ in ServerStats._fields_}
+
+    def trace(self, max_batches=1 << 20):
+        """Batch records of the run (SERVER_BATCH fields), oldest first."""
+        import numpy as np
+        out = np.zeros(max(int(max_batches), 1), dtype=SERVER_BATCH)
+        n = C.c_int64()
+        _check(lib.abp_server_trace(self.handle, out.ctypes.data_as(C.c_void_p), int(max_batches), C.byref(n)))
+        return out[: n.value]

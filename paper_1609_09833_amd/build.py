@@ -67,13 +67,33 @@ def build(verbose: bool = True, lib_path: str = LIB, extra=(), build_dir: str = 
                 raise RuntimeError(f"hipcc failed on {src}")
             objs.append(obj)
     tmp = lib_path + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-soname,libabp.so", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         print(r.stderr, file=sys.stderr)
         raise RuntimeError("link of libabp.so failed")
     os.replace(tmp, lib_path)
+    if lib_path == LIB:
+        build_driver()
     return lib_path
+
+
+DRIVER_SRC = os.path.join(PKG, "examples", "abp_serve_driver.cpp")
+DRIVER = os.path.join(PKG, "examples", "libabp_serve_driver.so")
+
+
+def build_driver() -> str:
+    """The serving load generator (a client of the C-ABI, not part of the
+    library): plain C++ against include/abp.h, linked to libabp.so."""
+    tmp = DRIVER + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE, DRIVER_SRC,
+           "-L", PKG, "-labp", "-Wl,-rpath,$ORIGIN/..", "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        print(r.stderr, file=sys.stderr)
+        raise RuntimeError("build of the serving driver failed")
+    os.replace(tmp, DRIVER)
+    return DRIVER
 
 
 if __name__ == "__main__":

@@ -35,6 +35,7 @@ struct abp_ctx {
   size_t fws_bytes = 0;
   void* wt_buf = nullptr;             // bias_deposit: bias at new centres (well-tempered heights)
   size_t wt_bytes = 0;
+  int32_t force_shape = ABP_SHAPE_AUTO;
 
   HistView hist() const {
     HistView h;
@@ -444,12 +445,20 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
   A.use_grid = mode == ABP_EVAL_GRID ? 1 : 0;
   A.grid = ctx->grid;
   A.prec = prec;
-  if (abp::force_uses_workspace(walkers->nw, ctx->committed, A.use_grid, 0)) {
+  A.shape = ctx->force_shape;
+  if (abp::force_uses_workspace(walkers->nw, ctx->committed, A.use_grid, 0, A.shape)) {
     const int nbw = abp::force_blocks_per_walker(ctx->committed, 0, 0);
     st = force_workspace(ctx, walkers->nw, nbw);
     if (st != ABP_OK) return st;
   }
   HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, ctx->fws, (hipStream_t)stream));
+  return ok();
+}
+
+abp_status abp_set_force_shape(abp_ctx* ctx, int32_t shape) {
+  if (!ctx) return fail(ABP_E_INVAL, "context is NULL");
+  if (shape < ABP_SHAPE_AUTO || shape > ABP_SHAPE_CHAIN) return fail(ABP_E_INVAL, "unknown force shape %d", shape);
+  ctx->force_shape = shape;
   return ok();
 }
 
@@ -530,6 +539,7 @@ const char* abp_status_str(abp_status status) {
     case ABP_E_DEVICE: return "ABP_E_DEVICE";
     case ABP_E_INDEX: return "ABP_E_INDEX";
     case ABP_E_NONFINITE: return "ABP_E_NONFINITE";
+    case ABP_E_BUSY: return "ABP_E_BUSY";
   }
   return "ABP_E_UNKNOWN";
 }
@@ -550,6 +560,12 @@ CtxView ctx_view(abp_ctx* ctx) {
 }
 
 int64_t ctx_reserved(const abp_ctx* ctx) { return ctx->reserved; }
+
+abp_status ctx_reserve_commit(abp_ctx* ctx, int64_t n) {
+  if (!ctx->grid || n <= 0) return ok();
+  DeviceGuard guard(ctx->device);
+  return grow_scratch(ctx, abp::grid_deposit_scratch_bytes(ctx->K, n));
+}
 
 abp_status set_error(abp_status st, const char* msg) {
   if (st == ABP_OK) return ok();

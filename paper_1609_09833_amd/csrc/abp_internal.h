@@ -128,6 +128,7 @@ struct ForceArgs {
   double* s;
   double* V;
   double* dVds;
+  int32_t shape;                   // abp_force_shape of the direct sum (ABP_SHAPE_AUTO: by size)
   int32_t cv_only;                 // 1: compute s only
   int32_t use_grid;
   int32_t prec;                    // abp_prec
@@ -148,7 +149,7 @@ __host__ __device__ inline int64_t force_chunks(int64_t nvis) { return (nvis + k
 // launch leaves at zero).
 constexpr size_t kForceArrivedBytes = 256;
 int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only);
-bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only);
+bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only, int shape);
 size_t force_workspace_bytes(int64_t nw, int nbw, int ndim);
 hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs& A, void* workspace,
                              hipStream_t stream);

@@ -21,10 +21,10 @@
 //   fused (a short history): one launch, the walker's block does the CV
 //     part, sums its own chunks and finishes;
 //   split (a long history): a CV launch, a sum launch of one wave per
-//     (chunk, 64 walkers) in which every lane sums the chunk at its walker's
-//     CV value with the hill records read as wave-uniform scalar loads (each
-//     fetched once per 64 walkers), and a finish launch that merges the
-//     chunk sums.
+//     (chunk, 64 walkers) that stages the chunk's 64 hill records in LDS (one
+//     coalesced load per lane, so each record is fetched once per 64 walkers)
+//     and in which every lane sums the chunk at its walker's CV value from
+//     LDS broadcasts, and a finish launch that merges the chunk sums.
 // So a walker's result is bitwise the same alone or in any batch, whichever
 // shape runs. No block waits for another; no atomics touch sums or forces.
 //
@@ -1181,14 +1181,13 @@ hipError_t launch_d(int mask, const FArgs& F, int shape, hipStream_t stream) {
 }
 
 // The launch shape of a direct-sum bias_force: fused (short histories), else
-// chained (one or two walkers) or split. ABP_FORCE_SHAPE=fused|split|chain
-// overrides the choice (for tests and tuning; chain applies to batches of up
-// to kChainCounters); all three give the same results.
-int direct_shape(int64_t nw, int64_t committed) {
-  const char* env = std::getenv("ABP_FORCE_SHAPE");
-  if (env && std::strcmp(env, "fused") == 0) return kShapeFused;
-  if (env && std::strcmp(env, "split") == 0) return kShapeSplit;
-  if (env && std::strcmp(env, "chain") == 0) return nw <= kChainCounters ? kShapeChain : kShapeSplit;
+// chained (one or two walkers) or split. `fixed` (an abp_force_shape other
+// than AUTO) overrides the choice; chain applies to batches of up to
+// kChainCounters. All three give the same results.
+int direct_shape(int64_t nw, int64_t committed, int fixed) {
+  if (fixed == ABP_SHAPE_FUSED) return kShapeFused;
+  if (fixed == ABP_SHAPE_SPLIT) return kShapeSplit;
+  if (fixed == ABP_SHAPE_CHAIN) return nw <= kChainCounters ? kShapeChain : kShapeSplit;
   if (committed <= kFusedMaxHills) return kShapeFused;
   return nw <= kChainMaxWalkers ? kShapeChain : kShapeSplit;
 }
@@ -1200,9 +1199,9 @@ int force_blocks_per_walker(int64_t committed, int use_grid, int cv_only) {
   return (int)force_chunks(committed);
 }
 
-bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only) {
+bool force_uses_workspace(int64_t nw, int64_t committed, int use_grid, int cv_only, int shape) {
   if (use_grid || cv_only) return false;
-  return direct_shape(nw, committed) != kShapeFused;
+  return direct_shape(nw, committed, shape) != kShapeFused;
 }
 
 // Layout: the chained shape's arrival counters (a fixed region at the start,
@@ -1235,7 +1234,7 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
   F.sbad = nullptr;
   F.part32 = nullptr;
   F.part64 = nullptr;
-  const bool split = force_uses_workspace(A.nw, F.committed, A.use_grid, A.cv_only);
+  const bool split = force_uses_workspace(A.nw, F.committed, A.use_grid, A.cv_only, A.shape);
   F.arrived = nullptr;
   if (split) {
     if (!workspace) return hipErrorInvalidValue;
@@ -1251,7 +1250,7 @@ hipError_t launch_bias_force(const Consts& K, const HistView& H, const ForceArgs
     F.part32 = reinterpret_cast<float2*>(p + st + en + sc);
     F.part64 = reinterpret_cast<double*>(p + st + en + sc);
   }
-  const int shape = (A.use_grid || A.cv_only) ? kShapeFused : (split ? direct_shape(A.nw, F.committed) : kShapeFused);
+  const int shape = (A.use_grid || A.cv_only) ? kShapeFused : (split ? direct_shape(A.nw, F.committed, A.shape) : kShapeFused);
   int mask = 0;
   for (int i = 0; i < K.ndim; ++i) mask |= (K.periodic[i] ? 1 : 0) << i;
   switch (K.ndim) {

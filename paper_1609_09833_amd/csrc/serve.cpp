@@ -1,34 +1,46 @@
 // Serving loop of libabp (abp_server_*): continuous batching of bias-force
 // requests from many walkers sharing one hill history.
 //
-// One host thread runs the scheduler. Each turn it
-//   1. releases requests whose arrival time has passed into per-walker FIFOs,
-//   2. retires finished batches (event polled): records completion times and
-//      outputs, frees the walkers for their next request, and commits history
-//      slots once every earlier slot is done,
-//   3. admits waiting walkers first come first served into the device pools,
+// A request is the per-step exchange of section "Minimization of
+// Interprocess Communications": a walker's engine submits the positions of
+// its CV atoms for one MD step and polls back the bias force on exactly those
+// atoms (and s, V, dV/ds).
+//
+// Threads. Callers submit and poll from any host threads. A scheduler thread,
+// started by abp_server_start, owns every device call. Each turn it
+//   1. takes newly submitted requests into per-walker FIFOs,
+//   2. retires finished batches (event polled): records results, hands them
+//      to the poll queue, frees the walkers for their next request, and
+//      commits history slots, in order, on one commit stream once every
+//      earlier slot is done (so grid deposits never overlap),
+//   3. admits waiting walkers first come first served into the device pool,
 //      evicting least recently used idle walkers when the budget is short,
-//   4. if a stream is free, forms a batch from the walkers that are resident,
-//      idle and have a request, and enqueues: descriptor upload (with the
-//      base positions and masses of the CV atoms of walkers admitted since
-//      their last batch, gathered here), the engine step (those stored into
-//      the pool, CV-atom positions for this step, cleared CV-atom forces), the
-//      bias-force stages (they write the outputs straight into mapped host
-//      memory), an event.
+//   4. if a batch slot is free, forms a batch from the walkers that are
+//      resident, idle and have a request, and enqueues on the slot's stream:
+//      the descriptor upload (with the masses of walkers admitted for it),
+//      the stage launch (positions from the requests' mapped host staging into
+//      the pool, forces cleared), the bias-force launches (they write s, V,
+//      dV/ds straight into mapped host memory), the gather launch (forces back
+//      to the requests' staging) and an event.
 // Requests in one batch see the same history version (hills committed when
 // the batch was formed); deposits go to slots reserved in formation order.
+// Every buffer is sized at start: the loop itself allocates nothing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <functional>
 #include <list>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "abp_serve_internal.h"
@@ -45,22 +57,37 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
   } while (0)
 
 constexpr int kMaxLists = 6;
-constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;   // ten FP32 pool arrays
+constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;
+constexpr int kPoolArrays = 7;                 // x, y, z, mass, fx, fy, fz
+constexpr size_t kTraceMax = (size_t)1 << 20;  // batch records kept
+constexpr double kSpinSeconds = 2e-3;          // idle time the scheduler spins before it sleeps
 
 struct Walker {
-  int32_t n = 0;
-  int64_t img_base = 0;      // first entry of the walker's CV image
-  int64_t entries = 0;       // CV-list entries, all lists
-  int64_t list_base = 0;     // offset in the list pool
+  int32_t n_atoms = 0;
+  int32_t n_cv = 0;          // distinct CV atoms
+  int64_t cv_base = 0;       // first entry in cv_atom / cv_mass
+  int64_t list_base = 0;     // first entry of its lists in the list pool (indices into its CV atoms)
   int32_t len[kMaxLists] = {0, 0, 0, 0, 0, 0};
-  int64_t atom_base = -1;    // device pool offset when resident
+  int64_t pool_off = -1;     // device pool offset while resident
   bool inflight = false;
-  bool waiting_admission = false;
+  bool waiting = false;
   bool in_ready = false;
-  bool fresh = false;
+  bool fresh = false;        // admitted since its last batch: masses go with the next one
   bool in_lru = false;
   std::list<int32_t>::iterator lru_it;
-  std::deque<int64_t> queue;  // request indices
+  std::deque<int32_t> queue; // request records, submission order
+};
+
+struct Record {              // one request from submit to poll
+  int64_t id = -1;
+  int32_t walker = -1;
+  int32_t n_cv = 0;
+  int64_t step = 0;
+  int64_t arena_off = 0;     // floats: x, y, z, fx, fy, fz blocks of n_cv each
+  float* force_out = nullptr;
+  double t_submit = 0.0, t_done = 0.0;
+  int64_t version = 0, dep_slot = -1;
+  double s[3] = {0, 0, 0}, V = 0.0, dV[3] = {0, 0, 0};
 };
 
 struct Slot {
@@ -69,41 +96,36 @@ struct Slot {
   bool busy = false;
   int64_t nb = 0;
   int64_t version = 0;
-  std::vector<int64_t> reqs;
-  std::vector<int64_t> dep_slots;   // history slot per request or -1
-  char* h_desc = nullptr;            // pinned descriptor, then the staged base positions
+  double t_formed = 0.0, t_launched = 0.0;
+  int32_t admitted = 0;
+  std::vector<int32_t> reqs;         // records
+  std::vector<int64_t> dep_slots;    // history slot per request or -1
+  char* h_desc = nullptr;            // pinned descriptor, then the staged masses
   char* d_desc = nullptr;
-  size_t desc_cap = 0;               // bytes of h_desc and of d_desc
+  size_t desc_cap = 0;
   double* h_out = nullptr;           // mapped pinned outputs: s[ncv][nb], V[nb], dV[ncv][nb]
-  double* m_out = nullptr;           // its device view: the bias-force launches write there directly
-  void* d_ws = nullptr;              // bias_force workspace
-  size_t ws_bytes = 0;
+  double* m_out = nullptr;           // its device view
+  void* d_ws = nullptr;              // bias_force workspace, sized for max_batch at the capacity
 };
 
 // Byte layout of a batch descriptor with nb requests (arrays packed at stride
-// nb). The staging area follows at `total`: (x0, y0, z0, mass) of the CV
-// entries of every walker admitted for this batch, in list order.
+// nb). The staged masses follow at `total`.
 struct DescLayout {
-  size_t atom_base, stage_off, step, dep_slot, dep_height, n_atoms, walker, list_beg, list_len, total;
+  size_t pool_off, arena_off, stage_off, dep_slot, dep_height, n_cv, list_beg, list_len, total;
   static size_t up(size_t x) { return (x + 15) / 16 * 16; }
   DescLayout(int64_t nb, int nlists) {
     size_t o = 0;
-    atom_base = o; o = up(o + 8 * nb);
+    pool_off = o; o = up(o + 8 * nb);
+    arena_off = o; o = up(o + 8 * nb);
     stage_off = o; o = up(o + 8 * nb);
-    step = o; o = up(o + 8 * nb);
     dep_slot = o; o = up(o + 8 * nb);
     dep_height = o; o = up(o + 8 * nb);
-    n_atoms = o; o = up(o + 4 * nb);
-    walker = o; o = up(o + 4 * nb);
+    n_cv = o; o = up(o + 4 * nb);
     list_beg = o; o = up(o + 4 * nb * nlists);
     list_len = o; o = up(o + 4 * nb * nlists);
     total = o;
   }
 };
-
-double now_s(std::chrono::steady_clock::time_point t0) {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
 
 }  // namespace
 
@@ -114,94 +136,73 @@ struct abp_server {
   int ncv = 0;
   int nlists = 0;
   int kind[3] = {0, 0, 0};
-  // registered walkers (host copies until the first replay)
+  std::chrono::steady_clock::time_point t0;
+  // registration (host)
   std::vector<Walker> walkers;
-  // CV images: (x0, y0, z0, mass) of every walker's CV-list entries, in list
-  // order (the only atoms the engine step and the bias path touch)
-  std::vector<float4> himg;
-  std::vector<int32_t> lidx;
-  std::vector<float> lrx, lry, lrz;
-  bool dirty = true;
-  // device list pool
+  std::vector<int32_t> cv_atom;      // every walker's CV atoms (walker-local indices, increasing)
+  std::vector<float> cv_mass;        // and their masses
+  std::vector<int32_t> lidx;         // every walker's lists, as positions among its CV atoms
+  std::vector<float> lrx, lry, lrz;  // RMSD references aligned with lidx
+  int32_t max_cv = 0;
+  bool registered = false;           // start has run once: the lists are on the device
+  // device state
   int32_t* d_lidx = nullptr;
-  float* d_rx = nullptr; float* d_ry = nullptr; float* d_rz = nullptr;
-  // device atom pools
+  float* d_rx = nullptr;
+  float* d_ry = nullptr;
+  float* d_rz = nullptr;
   int64_t pool_atoms = 0;
-  float* d_pool = nullptr;           // 10 arrays of pool_atoms floats
-  abp::RangePool free_atoms;         // free atom ranges of the pools (best fit: admissions are
-                                     // frequent and the pools fragment)
+  float* d_pool = nullptr;           // kPoolArrays arrays of pool_atoms floats
+  abp::RangePool free_atoms;         // free pool ranges, best fit
   std::list<int32_t> lru;            // idle resident walkers, least recent first
   std::deque<int32_t> admission;     // walkers waiting for memory
   std::deque<int32_t> ready;         // resident, idle, with a request
   std::vector<Slot> slots;
   std::deque<int> launch_order;      // busy slots in launch order
-  // deposit commit bookkeeping
+  hipStream_t commit_stream = nullptr;
   std::map<int64_t, bool> dep_done;  // reserved slot -> done
   int64_t resident = 0;
+  // request staging: max_pending records, each with a fixed range of the
+  // pinned, mapped arena (6 * max_cv floats)
+  float* arena = nullptr;
+  float* d_arena = nullptr;
+  int64_t stride = 0;
+  std::vector<Record> records;
+  // shared between the callers and the scheduler
+  std::mutex mu_in;                  // incoming, free_records, next_id
+  std::condition_variable cv_in;
+  std::vector<int32_t> incoming;
+  std::vector<int32_t> free_records;
+  int64_t next_id = 0;
+  std::mutex mu_out;                 // completed
+  std::condition_variable cv_out;
+  std::deque<int32_t> completed;
+  std::atomic<int64_t> outstanding{0};   // submitted and not yet completed
+  std::atomic<bool> running{false};
+  std::atomic<bool> stopping{false};
+  std::thread thread;
+  std::string thread_error;          // set by the scheduler when it fails (read after join)
+  abp_status thread_status = ABP_OK;
+  // statistics (written by the scheduler under mu_stats)
+  std::mutex mu_stats;
   abp_server_stats stats{};
+  double t_start = 0.0, t_stop = -1.0;
+  std::vector<abp_server_batch> trace;
+  size_t trace_next = 0;
 };
 
 namespace {
 
+double now_s(const abp_server* S) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+}
+
 float* pool_array(abp_server* S, int which) { return S->d_pool + (int64_t)which * S->pool_atoms; }
-
-bool pool_alloc(abp_server* S, int64_t n, int64_t* off) { return S->free_atoms.alloc(n, off); }
-
-void pool_free(abp_server* S, int64_t off, int64_t n) { S->free_atoms.free(off, n); }
-
-// Descriptor buffers of every stream, sized once per replay for the largest
-// staging a batch can need: the max_batch walkers with the most CV entries,
-// all just admitted (never more than all walkers' CV images together). The
-// slots must be idle.
-abp_status size_descriptors(abp_server* S) {
-  std::vector<int64_t> ent;
-  ent.reserve(S->walkers.size());
-  for (const auto& w : S->walkers) ent.push_back(w.entries);
-  const size_t b = std::min(ent.size(), (size_t)S->desc.max_batch);
-  std::partial_sort(ent.begin(), ent.begin() + b, ent.end(), std::greater<int64_t>());
-  int64_t most = 0;
-  for (size_t i = 0; i < b; ++i) most += ent[i];
-  const size_t need = DescLayout(S->desc.max_batch, S->nlists).total + (size_t)most * sizeof(float4);
-  for (auto& sl : S->slots) {
-    if (sl.desc_cap >= need) continue;
-    SRV_TRY(hipHostFree(sl.h_desc));
-    SRV_TRY(hipFree(sl.d_desc));
-    sl.h_desc = nullptr;
-    sl.d_desc = nullptr;
-    sl.desc_cap = 0;
-    SRV_TRY(hipHostMalloc((void**)&sl.h_desc, need, hipHostMallocDefault));
-    SRV_TRY(hipMalloc((void**)&sl.d_desc, need));
-    sl.desc_cap = need;
-  }
-  return ABP_OK;
-}
-
-abp_status finalize(abp_server* S) {
-  if (!S->dirty) return ABP_OK;
-  const size_t nl = S->lidx.size();
-  if (S->d_lidx) { (void)hipFree(S->d_lidx); S->d_lidx = nullptr; }
-  if (S->d_rx) { (void)hipFree(S->d_rx); S->d_rx = nullptr; }
-  if (S->d_ry) { (void)hipFree(S->d_ry); S->d_ry = nullptr; }
-  if (S->d_rz) { (void)hipFree(S->d_rz); S->d_rz = nullptr; }
-  SRV_TRY(hipMalloc(&S->d_lidx, sizeof(int32_t) * (nl + 1)));
-  SRV_TRY(hipMalloc(&S->d_rx, sizeof(float) * (nl + 1)));
-  SRV_TRY(hipMalloc(&S->d_ry, sizeof(float) * (nl + 1)));
-  SRV_TRY(hipMalloc(&S->d_rz, sizeof(float) * (nl + 1)));
-  if (nl) {
-    SRV_TRY(hipMemcpy(S->d_lidx, S->lidx.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice));
-    SRV_TRY(hipMemcpy(S->d_rx, S->lrx.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
-    SRV_TRY(hipMemcpy(S->d_ry, S->lry.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
-    SRV_TRY(hipMemcpy(S->d_rz, S->lrz.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
-  }
-  S->dirty = false;
-  return ABP_OK;
-}
 
 // Returns every resident walker to the pool and clears all queues.
 void reset_residency(abp_server* S) {
   for (auto& w : S->walkers) {
-    w.atom_base = -1;
-    w.inflight = w.waiting_admission = w.in_ready = w.fresh = w.in_lru = false;
+    w.pool_off = -1;
+    w.inflight = w.waiting = w.in_ready = w.fresh = w.in_lru = false;
     w.queue.clear();
   }
   S->free_atoms.reset(S->pool_atoms);
@@ -213,7 +214,7 @@ void reset_residency(abp_server* S) {
 
 void make_ready(abp_server* S, int32_t wid) {
   Walker& w = S->walkers[wid];
-  if (w.in_ready || w.inflight || w.atom_base < 0 || w.queue.empty()) return;
+  if (w.in_ready || w.inflight || w.pool_off < 0 || w.queue.empty()) return;
   if (w.in_lru) {
     S->lru.erase(w.lru_it);
     w.in_lru = false;
@@ -224,7 +225,7 @@ void make_ready(abp_server* S, int32_t wid) {
 
 void make_idle(abp_server* S, int32_t wid) {
   Walker& w = S->walkers[wid];
-  if (w.in_lru || w.atom_base < 0) return;
+  if (w.in_lru || w.pool_off < 0) return;
   S->lru.push_back(wid);
   w.lru_it = std::prev(S->lru.end());
   w.in_lru = true;
@@ -236,41 +237,404 @@ void admit(abp_server* S) {
     const int32_t wid = S->admission.front();
     Walker& w = S->walkers[wid];
     int64_t off;
-    bool ok = pool_alloc(S, w.n, &off);
+    bool ok = S->free_atoms.alloc(w.n_cv, &off);
     while (!ok && !S->lru.empty()) {
       const int32_t victim = S->lru.front();
       S->lru.pop_front();
       Walker& v = S->walkers[victim];
       v.in_lru = false;
-      pool_free(S, v.atom_base, v.n);
-      v.atom_base = -1;
+      S->free_atoms.free(v.pool_off, v.n_cv);
+      v.pool_off = -1;
+      v.fresh = false;
       S->resident--;
-      S->stats.evictions++;
-      ok = pool_alloc(S, w.n, &off);
+      {
+        std::lock_guard<std::mutex> lk(S->mu_stats);
+        S->stats.evictions++;
+      }
+      ok = S->free_atoms.alloc(w.n_cv, &off);
     }
     if (!ok) return;                       // wait for a walker to go idle
     S->admission.pop_front();
-    w.waiting_admission = false;
-    w.atom_base = off;
+    w.waiting = false;
+    w.pool_off = off;
     w.fresh = true;
     S->resident++;
+    std::lock_guard<std::mutex> lk(S->mu_stats);
     S->stats.admissions++;
     if (S->resident > S->stats.peak_resident) S->stats.peak_resident = S->resident;
     make_ready(S, wid);
   }
 }
 
-void commit_prefix(abp_server* S, hipStream_t stream) {
+// Commits the longest done prefix of reserved slots, on the commit stream
+// (one stream, so the grid deposits of successive commits never overlap).
+abp_status commit_prefix(abp_server* S) {
   int64_t upto = abp_num_hills(S->ctx);
   auto it = S->dep_done.begin();
   while (it != S->dep_done.end() && it->first == upto && it->second) {
     ++upto;
     it = S->dep_done.erase(it);
   }
-  if (upto > abp_num_hills(S->ctx)) {
-    const int64_t before = abp_num_hills(S->ctx);
-    if (abp_commit(S->ctx, upto, stream) == ABP_OK) S->stats.deposits += upto - before;
+  const int64_t before = abp_num_hills(S->ctx);
+  if (upto > before) {
+    const abp_status st = abp_commit(S->ctx, upto, S->commit_stream);
+    if (st != ABP_OK) return st;
+    std::lock_guard<std::mutex> lk(S->mu_stats);
+    S->stats.deposits += upto - before;
   }
+  return ABP_OK;
+}
+
+// Enqueues one batch on slot `sl`: requests recs[j] of walkers wids[j] (all
+// resident and marked in flight by the caller). shape: abp_force_shape of the
+// bias-force launches; deposits: whether deposit steps reserve slots.
+abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int32_t* recs, int64_t nb,
+                         int32_t shape, bool deposits) {
+  DescLayout L(nb, S->nlists);
+  int64_t* d_pool = reinterpret_cast<int64_t*>(sl.h_desc + L.pool_off);
+  int64_t* d_arena = reinterpret_cast<int64_t*>(sl.h_desc + L.arena_off);
+  int64_t* d_stage = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
+  int64_t* d_dep = reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
+  double* d_hgt = reinterpret_cast<double*>(sl.h_desc + L.dep_height);
+  int32_t* d_ncv = reinterpret_cast<int32_t*>(sl.h_desc + L.n_cv);
+  int32_t* d_lbeg = reinterpret_cast<int32_t*>(sl.h_desc + L.list_beg);
+  int32_t* d_llen = reinterpret_cast<int32_t*>(sl.h_desc + L.list_len);
+  float* h_stage = reinterpret_cast<float*>(sl.h_desc + L.total);
+  int64_t spos = 0;
+  bool any_deposit = false;
+  sl.reqs.clear();
+  sl.dep_slots.clear();
+  sl.admitted = 0;
+  sl.version = abp_num_hills(S->ctx);
+  for (int64_t j = 0; j < nb; ++j) {
+    Walker& w = S->walkers[wids[j]];
+    const Record& R = S->records[recs[j]];
+    sl.reqs.push_back(recs[j]);
+    d_pool[j] = w.pool_off;
+    d_arena[j] = R.arena_off;
+    d_ncv[j] = w.n_cv;
+    d_stage[j] = -1;
+    if (w.fresh) {
+      if (L.total + (size_t)(spos + w.n_cv) * sizeof(float) > sl.desc_cap)
+        return sfail(ABP_E_DEVICE, "batch descriptor larger than sized (internal error)");
+      d_stage[j] = spos;
+      std::memcpy(h_stage + spos, S->cv_mass.data() + w.cv_base, sizeof(float) * (size_t)w.n_cv);
+      spos += w.n_cv;
+      w.fresh = false;
+      sl.admitted++;
+    }
+    int64_t lpos = w.list_base;
+    for (int q = 0; q < S->nlists; ++q) {
+      d_lbeg[q * nb + j] = (int32_t)lpos;
+      d_llen[q * nb + j] = w.len[q];
+      lpos += w.len[q];
+    }
+    int64_t slot = -1;
+    const int64_t step = R.step;
+    if (deposits && S->desc.deposit_every > 0 && step > 0 && step % S->desc.deposit_every == 0) {
+      if (abp_reserve(S->ctx, 1, &slot) != ABP_OK) slot = -1;     // history full: no deposit
+      if (slot >= 0) {
+        S->dep_done[slot] = false;
+        any_deposit = true;
+      }
+    }
+    d_dep[j] = slot;
+    d_hgt[j] = S->desc.height_decay > 0
+                   ? S->desc.height0 * std::exp(-(double)std::max<int64_t>(slot, 0) / S->desc.height_decay)
+                   : S->desc.height0;
+    sl.dep_slots.push_back(slot);
+  }
+  sl.nb = nb;
+  SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float), hipMemcpyHostToDevice,
+                         sl.stream));
+  abp::ServeArgs E;
+  E.nb = nb;
+  E.pool_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.pool_off);
+  E.arena_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.arena_off);
+  E.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
+  E.n_cv = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_cv);
+  E.stage_mass = reinterpret_cast<const float*>(sl.d_desc + L.total);
+  E.arena = S->d_arena;
+  E.x = pool_array(S, 0);
+  E.y = pool_array(S, 1);
+  E.z = pool_array(S, 2);
+  E.mass = pool_array(S, 3);
+  E.fx = pool_array(S, 4);
+  E.fy = pool_array(S, 5);
+  E.fz = pool_array(S, 6);
+  SRV_TRY(abp::launch_serve_stage(E, sl.stream));
+  abp::ForceArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.ncv = S->ncv;
+  for (int a = 0; a < 3; ++a) A.kind[a] = S->kind[a];
+  A.list_beg = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_beg);
+  A.list_len = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_len);
+  A.list_idx = S->d_lidx;
+  A.ref_x = S->d_rx;
+  A.ref_y = S->d_ry;
+  A.ref_z = S->d_rz;
+  A.nw = nb;
+  A.atom_base = E.pool_off;
+  A.n_atoms = E.n_cv;
+  A.x = E.x;
+  A.y = E.y;
+  A.z = E.z;
+  A.mass = E.mass;
+  A.fx = E.fx;
+  A.fy = E.fy;
+  A.fz = E.fz;
+  A.n_visible = nullptr;
+  A.n_visible_default = sl.version;
+  A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(sl.d_desc + L.dep_slot) : nullptr;
+  A.deposit_height = reinterpret_cast<const double*>(sl.d_desc + L.dep_height);
+  A.s = sl.m_out;
+  A.V = sl.m_out + S->ncv * nb;
+  A.dVds = sl.m_out + (S->ncv + 1) * nb;
+  A.prec = S->desc.prec;
+  A.shape = shape;
+  A.err = S->cv.err;
+  SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
+  SRV_TRY(abp::launch_serve_gather(E, sl.stream));
+  SRV_TRY(hipEventRecord(sl.done, sl.stream));
+  sl.busy = true;
+  return ABP_OK;
+}
+
+void record_batch(abp_server* S, const Slot& sl, int slot_index, double t_done) {
+  abp_server_batch b;
+  b.t_formed = sl.t_formed;
+  b.t_launched = sl.t_launched;
+  b.t_done = t_done;
+  b.requests = sl.nb;
+  b.version = sl.version;
+  b.slot = slot_index;
+  b.admitted = sl.admitted;
+  std::lock_guard<std::mutex> lk(S->mu_stats);
+  if (S->trace.size() < kTraceMax) S->trace.push_back(b);
+  else S->trace[S->trace_next % kTraceMax] = b;
+  S->trace_next++;
+}
+
+bool nothing_to_do(const abp_server* S) {
+  return S->launch_order.empty() && S->ready.empty() && S->admission.empty();
+}
+
+// One scheduler turn's device work (steps 2-4). Returns false on failure
+// (S->thread_status / thread_error set).
+bool turn(abp_server* S) {
+  const int ncv = S->ncv;
+  // 2. retire finished batches, in launch order
+  while (!S->launch_order.empty()) {
+    const int idx = S->launch_order.front();
+    Slot& sl = S->slots[idx];
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) {
+      S->thread_status = ABP_E_DEVICE;
+      S->thread_error = std::string("batch failed: ") + hipGetErrorString(q);
+      return false;
+    }
+    const double td = now_s(S);
+    const int64_t nb = sl.nb;
+    for (int64_t j = 0; j < nb; ++j) {
+      Record& R = S->records[sl.reqs[j]];
+      R.t_done = td;
+      R.version = sl.version;
+      R.dep_slot = sl.dep_slots[j];
+      for (int a = 0; a < ncv; ++a) {
+        R.s[a] = sl.h_out[a * nb + j];
+        R.dV[a] = sl.h_out[(ncv + 1 + a) * nb + j];
+      }
+      R.V = sl.h_out[ncv * nb + j];
+      Walker& w = S->walkers[R.walker];
+      w.inflight = false;
+      if (w.queue.empty()) make_idle(S, R.walker);
+      else make_ready(S, R.walker);
+      if (sl.dep_slots[j] >= 0) S->dep_done[sl.dep_slots[j]] = true;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu_out);
+      for (int64_t j = 0; j < nb; ++j) S->completed.push_back(sl.reqs[j]);
+    }
+    S->cv_out.notify_all();
+    S->outstanding.fetch_sub(nb);
+    {
+      std::lock_guard<std::mutex> lk(S->mu_stats);
+      S->stats.completed += nb;
+    }
+    record_batch(S, sl, idx, td);
+    sl.busy = false;
+    S->launch_order.pop_front();
+    const abp_status st = commit_prefix(S);
+    if (st != ABP_OK) {
+      S->thread_status = st;
+      S->thread_error = abp_last_error();
+      return false;
+    }
+  }
+  // 3. admission
+  admit(S);
+  // 4. form and launch a batch on a free slot
+  if (S->ready.empty()) return true;
+  int free_slot = -1;
+  for (int k = 0; k < (int)S->slots.size(); ++k)
+    if (!S->slots[k].busy) { free_slot = k; break; }
+  if (free_slot < 0) return true;
+  Slot& sl = S->slots[free_slot];
+  sl.t_formed = now_s(S);
+  const int64_t nb = std::min<int64_t>((int64_t)S->ready.size(), S->desc.max_batch);
+  std::vector<int32_t> wids(nb), recs(nb);
+  for (int64_t j = 0; j < nb; ++j) {
+    const int32_t wid = S->ready.front();
+    S->ready.pop_front();
+    Walker& w = S->walkers[wid];
+    w.in_ready = false;
+    w.inflight = true;
+    wids[j] = wid;
+    recs[j] = w.queue.front();
+    w.queue.pop_front();
+  }
+  const abp_status st = enqueue_batch(S, sl, wids.data(), recs.data(), nb, ABP_SHAPE_AUTO, true);
+  if (st != ABP_OK) {
+    S->thread_status = st;
+    S->thread_error = abp_last_error();
+    return false;
+  }
+  sl.t_launched = now_s(S);
+  S->launch_order.push_back(free_slot);
+  std::lock_guard<std::mutex> lk(S->mu_stats);
+  S->stats.batches++;
+  if (nb > S->stats.max_batch_seen) S->stats.max_batch_seen = nb;
+  return true;
+}
+
+void scheduler(abp_server* S) {
+  if (hipSetDevice(S->cv.device) != hipSuccess) {
+    S->thread_status = ABP_E_DEVICE;
+    S->thread_error = "cannot select the context's device";
+    S->running = false;
+    return;
+  }
+  std::vector<int32_t> in;
+  double idle_since = -1.0;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu_in);
+      if (S->incoming.empty() && nothing_to_do(S)) {
+        if (S->stopping.load() && S->outstanding.load() == 0) break;
+        const double t = now_s(S);
+        if (idle_since < 0.0) idle_since = t;
+        if (t - idle_since > kSpinSeconds)
+          S->cv_in.wait_for(lk, std::chrono::milliseconds(1),
+                            [S] { return !S->incoming.empty() || S->stopping.load(); });
+      } else {
+        idle_since = -1.0;
+      }
+      in.swap(S->incoming);
+    }
+    // 1. intake, in submission order
+    for (const int32_t r : in) {
+      const int32_t wid = S->records[r].walker;
+      Walker& w = S->walkers[wid];
+      w.queue.push_back(r);
+      if (w.pool_off < 0) {
+        if (!w.waiting) {
+          w.waiting = true;
+          S->admission.push_back(wid);
+        }
+      } else {
+        make_ready(S, wid);
+      }
+    }
+    in.clear();
+    if (!turn(S)) break;
+  }
+  // drain what is in flight (after a failure too), so no kernel outlives the thread
+  for (auto& sl : S->slots) (void)hipStreamSynchronize(sl.stream);
+  (void)hipStreamSynchronize(S->commit_stream);
+  S->running = false;
+  S->cv_out.notify_all();
+}
+
+// Sizes every buffer of a run: descriptors (max_batch requests, the masses of
+// the max_batch walkers with the most CV atoms), the request arena, the
+// slots' bias-force workspaces for the history's capacity, the context's
+// grid-deposit scratch for the largest commit.
+abp_status size_buffers(abp_server* S) {
+  std::vector<int64_t> ncv;
+  ncv.reserve(S->walkers.size());
+  for (const auto& w : S->walkers) ncv.push_back(w.n_cv);
+  const size_t b = std::min(ncv.size(), (size_t)S->desc.max_batch);
+  std::partial_sort(ncv.begin(), ncv.begin() + b, ncv.end(), std::greater<int64_t>());
+  int64_t most = 0;
+  for (size_t i = 0; i < b; ++i) most += ncv[i];
+  const size_t need = DescLayout(S->desc.max_batch, S->nlists).total + (size_t)most * sizeof(float);
+  for (auto& sl : S->slots) {
+    if (sl.desc_cap >= need) continue;
+    if (sl.h_desc) SRV_TRY(hipHostFree(sl.h_desc));
+    if (sl.d_desc) SRV_TRY(hipFree(sl.d_desc));
+    sl.h_desc = nullptr;
+    sl.d_desc = nullptr;
+    sl.desc_cap = 0;
+    if (hipHostMalloc((void**)&sl.h_desc, need, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&sl.d_desc, need) != hipSuccess)
+      return sfail(ABP_E_NOMEM, "cannot allocate batch descriptors");
+    sl.desc_cap = need;
+  }
+  const int64_t stride = 6 * (int64_t)std::max(S->max_cv, 1);
+  if (stride != S->stride || !S->arena) {
+    if (S->arena) SRV_TRY(hipHostFree(S->arena));
+    S->arena = nullptr;
+    S->d_arena = nullptr;
+    const size_t bytes = sizeof(float) * (size_t)stride * (size_t)S->desc.max_pending;
+    if (hipHostMalloc((void**)&S->arena, bytes, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&S->d_arena, S->arena, 0) != hipSuccess)
+      return sfail(ABP_E_NOMEM, "cannot allocate the request staging");
+    S->stride = stride;
+  }
+  S->records.assign(S->desc.max_pending, Record());
+  S->free_records.clear();
+  for (int32_t r = S->desc.max_pending - 1; r >= 0; --r) {
+    S->records[r].arena_off = (int64_t)r * stride;
+    S->free_records.push_back(r);
+  }
+  const abp_status st = abp::ctx_reserve_commit(S->ctx, (int64_t)S->desc.max_batch * S->desc.streams);
+  if (st != ABP_OK) return st;
+  return ABP_OK;
+}
+
+// One batch of each launch shape for walker 0 at zero positions (a COM
+// distance and a torsion at coincident atoms have zero gradient by the
+// singular-point rule), so every kernel the loop can launch is loaded before
+// the first request (with no hills yet only the fused shape sums anything).
+// No deposit; results are discarded.
+abp_status warm_up(abp_server* S) {
+  if (S->walkers.empty()) return ABP_OK;
+  reset_residency(S);
+  Walker& w = S->walkers[0];
+  int64_t off;
+  if (!S->free_atoms.alloc(w.n_cv, &off)) return ABP_OK;
+  w.pool_off = off;
+  const int32_t rec = S->free_records.back();
+  Record& R = S->records[rec];
+  R.walker = 0;
+  R.n_cv = w.n_cv;
+  R.step = 0;
+  std::memset(S->arena + R.arena_off, 0, sizeof(float) * 6 * (size_t)w.n_cv);
+  const int32_t wid = 0;
+  Slot& sl = S->slots[0];
+  const int nshapes = abp_num_hills(S->ctx) > 0 ? 3 : 1;
+  const int32_t shapes[3] = {ABP_SHAPE_FUSED, ABP_SHAPE_SPLIT, ABP_SHAPE_CHAIN};
+  for (int k = 0; k < nshapes; ++k) {
+    const int32_t shape = shapes[k];
+    w.fresh = true;
+    const abp_status st = enqueue_batch(S, sl, &wid, &rec, 1, shape, false);
+    if (st != ABP_OK) return st;
+    SRV_TRY(hipStreamSynchronize(sl.stream));
+    sl.busy = false;
+  }
+  reset_residency(S);
+  return ABP_OK;
 }
 
 }  // namespace
@@ -291,11 +655,13 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
   if (desc->prec != ABP_PREC_FP32_KAHAN && desc->prec != ABP_PREC_FP32_NAIVE && desc->prec != ABP_PREC_FP64)
     return sfail(ABP_E_INVAL, "unknown precision");
   if (!(desc->hbm_budget_bytes >= kBytesPerAtom)) return sfail(ABP_E_INVAL, "budget too small");
-  if (!std::isfinite(desc->height0) || desc->height0 < 0 || !(desc->height_decay >= 0))
+  if (!std::isfinite(desc->height0) || desc->height0 < 0 || !(desc->height_decay >= 0) ||
+      !std::isfinite(desc->height_decay))
     return sfail(ABP_E_INVAL, "bad deposit height law");
-  if (!(desc->amplitude >= 0.0f) || !std::isfinite(desc->amplitude)) return sfail(ABP_E_INVAL, "bad amplitude");
+  if (desc->max_pending < 1 || desc->max_pending > (1 << 24)) return sfail(ABP_E_INVAL, "max_pending must be 1..2^24");
   abp_server* S = new (std::nothrow) abp_server();
   if (!S) return sfail(ABP_E_NOMEM, "host allocation failed");
+  S->t0 = std::chrono::steady_clock::now();
   S->ctx = ctx;
   S->cv = abp::ctx_view(ctx);
   S->desc = *desc;
@@ -318,46 +684,56 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     return sfail(ABP_E_DEVICE, "cannot select the context's device");
   }
   S->pool_atoms = desc->hbm_budget_bytes / kBytesPerAtom;
-  if (hipMalloc(&S->d_pool, sizeof(float) * 10 * S->pool_atoms) != hipSuccess) {
+  if (hipMalloc(&S->d_pool, sizeof(float) * kPoolArrays * S->pool_atoms) != hipSuccess) {
     delete S;
     return sfail(ABP_E_NOMEM, "cannot allocate the walker pool");
   }
   S->stats.pool_atoms = S->pool_atoms;
   reset_residency(S);
   const int64_t B = desc->max_batch;
-  DescLayout L(B, S->nlists);
+  const size_t ws = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
   S->slots.resize(desc->streams);
+  bool good = hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) == hipSuccess;
   for (auto& sl : S->slots) {
-    bool good = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
-                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-                hipHostMalloc((void**)&sl.h_desc, L.total, hipHostMallocDefault) == hipSuccess &&
-                hipMalloc((void**)&sl.d_desc, L.total) == hipSuccess &&
-                hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocMapped) == hipSuccess &&
-                hipHostGetDevicePointer((void**)&sl.m_out, sl.h_out, 0) == hipSuccess;
-    if (!good) {
-      abp_server_destroy(S);
-      return sfail(ABP_E_NOMEM, "cannot allocate per-stream batch buffers");
-    }
-    sl.desc_cap = L.total;
+    good = good && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+           hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocMapped) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&sl.m_out, sl.h_out, 0) == hipSuccess &&
+           hipMalloc(&sl.d_ws, ws) == hipSuccess && hipMemset(sl.d_ws, 0, ws) == hipSuccess;
     sl.reqs.reserve(B);
     sl.dep_slots.reserve(B);
-    // Workspace for a full batch at the history's capacity (split shape), so
-    // the loop never reallocates; it still grows on demand if this fails.
-    const size_t full = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
-    if (full <= ((size_t)1 << 30) && hipMalloc(&sl.d_ws, full) == hipSuccess &&
-        hipMemset(sl.d_ws, 0, full) == hipSuccess)
-      sl.ws_bytes = full;
-    else if (sl.d_ws) {
-      (void)hipFree(sl.d_ws);
-      sl.d_ws = nullptr;
-    }
+  }
+  if (!good) {
+    abp_server_destroy(S);
+    return sfail(ABP_E_NOMEM, "cannot allocate per-slot batch buffers and workspaces");
   }
   *out = S;
   return ABP_OK;
 }
 
+abp_status abp_server_stop(abp_server* S) {
+  if (!S) return sfail(ABP_E_INVAL, "NULL argument");
+  if (S->thread.joinable()) {
+    S->stopping = true;
+    S->cv_in.notify_all();
+    S->thread.join();
+    std::lock_guard<std::mutex> lk(S->mu_stats);
+    S->t_stop = now_s(S);
+    S->stats.wall_seconds = S->t_stop - S->t_start;
+  }
+  S->running = false;
+  if (S->thread_status != ABP_OK) {
+    const abp_status st = S->thread_status;
+    S->thread_status = ABP_OK;
+    return sfail(st, S->thread_error);
+  }
+  // Device-side flags of the run (invalid walker, non-finite input) surface here.
+  return abp_sync(S->ctx, nullptr);
+}
+
 abp_status abp_server_destroy(abp_server* S) {
   if (!S) return ABP_OK;
+  if (S->thread.joinable()) (void)abp_server_stop(S);
   (void)hipSetDevice(S->cv.device);
   for (auto& sl : S->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
@@ -368,6 +744,11 @@ abp_status abp_server_destroy(abp_server* S) {
     if (sl.h_out) (void)hipHostFree(sl.h_out);
     if (sl.d_ws) (void)hipFree(sl.d_ws);
   }
+  if (S->commit_stream) {
+    (void)hipStreamSynchronize(S->commit_stream);
+    (void)hipStreamDestroy(S->commit_stream);
+  }
+  if (S->arena) (void)hipHostFree(S->arena);
   if (S->d_lidx) (void)hipFree(S->d_lidx);
   if (S->d_rx) (void)hipFree(S->d_rx);
   if (S->d_ry) (void)hipFree(S->d_ry);
@@ -377,13 +758,12 @@ abp_status abp_server_destroy(abp_server* S) {
   return ABP_OK;
 }
 
-abp_status abp_server_add_walker(abp_server* S, int32_t n_atoms, const float* x0, const float* y0,
-                                 const float* z0, const float* mass, const int32_t* list_len,
+abp_status abp_server_add_walker(abp_server* S, int32_t n_atoms, const float* mass, const int32_t* list_len,
                                  const int32_t* list_idx, const float* ref_x, const float* ref_y,
-                                 const float* ref_z, int32_t* walker_id) {
-  if (!S || !x0 || !y0 || !z0 || !mass || !list_len || !walker_id) return sfail(ABP_E_INVAL, "NULL argument");
+                                 const float* ref_z, int32_t* walker_id, int32_t* n_cv_atoms) {
+  if (!S || !mass || !list_len || !walker_id) return sfail(ABP_E_INVAL, "NULL argument");
+  if (S->registered) return sfail(ABP_E_INVAL, "walkers are registered before abp_server_start");
   if (n_atoms < 1) return sfail(ABP_E_INVAL, "n_atoms must be >= 1");
-  if ((int64_t)n_atoms > S->pool_atoms) return sfail(ABP_E_NOMEM, "walker larger than the whole budget");
   int64_t total = 0;
   for (int q = 0; q < S->nlists; ++q) {
     if (list_len[q] < 0) return sfail(ABP_E_INVAL, "negative list length");
@@ -414,286 +794,216 @@ abp_status abp_server_add_walker(abp_server* S, int32_t n_atoms, const float* x0
     rmsd = rmsd || kind == ABP_CV_RMSD_OFF;
   }
   if (rmsd && (!ref_x || !ref_y || !ref_z)) return sfail(ABP_E_INVAL, "RMSD needs reference positions");
+  // the walker's CV atoms: distinct list atoms in increasing order
+  std::vector<int32_t> atoms(list_idx, list_idx + total);
+  std::sort(atoms.begin(), atoms.end());
+  atoms.erase(std::unique(atoms.begin(), atoms.end()), atoms.end());
+  const int32_t ncv_atoms = (int32_t)atoms.size();
+  if ((int64_t)ncv_atoms > S->pool_atoms) return sfail(ABP_E_NOMEM, "walker's CV atoms exceed the whole budget");
+  for (const int32_t i : atoms)
+    if (!std::isfinite(mass[i]) || !(mass[i] > 0.0f)) return sfail(ABP_E_INVAL, "CV-atom masses must be finite and > 0");
   Walker w;
-  w.n = n_atoms;
-  w.img_base = (int64_t)S->himg.size();
-  w.entries = total;
+  w.n_atoms = n_atoms;
+  w.n_cv = ncv_atoms;
+  w.cv_base = (int64_t)S->cv_atom.size();
   w.list_base = (int64_t)S->lidx.size();
   for (int q = 0; q < S->nlists; ++q) w.len[q] = list_len[q];
+  for (const int32_t i : atoms) {
+    S->cv_atom.push_back(i);
+    S->cv_mass.push_back(mass[i]);
+  }
   for (int64_t e = 0; e < total; ++e) {
-    const int32_t i = list_idx[e];
-    S->himg.push_back(make_float4(x0[i], y0[i], z0[i], mass[i]));
-    S->lidx.push_back(i);
+    const int32_t c = (int32_t)(std::lower_bound(atoms.begin(), atoms.end(), list_idx[e]) - atoms.begin());
+    S->lidx.push_back(c);
     S->lrx.push_back(ref_x ? ref_x[e] : 0.0f);
     S->lry.push_back(ref_y ? ref_y[e] : 0.0f);
     S->lrz.push_back(ref_z ? ref_z[e] : 0.0f);
   }
+  S->max_cv = std::max(S->max_cv, ncv_atoms);
   *walker_id = (int32_t)S->walkers.size();
+  if (n_cv_atoms) *n_cv_atoms = ncv_atoms;
   S->walkers.push_back(std::move(w));
-  S->dirty = true;
   return ABP_OK;
 }
 
-abp_status abp_server_replay(abp_server* S, int64_t n, const int32_t* walker, const int64_t* step,
-                             const double* t_arrival, double* t_done, int64_t* version, int64_t* deposit_slot,
-                             double* s_out, double* V_out, double* dV_out) {
-  if (!S || n < 0 || (n > 0 && (!walker || !step || !t_arrival))) return sfail(ABP_E_INVAL, "bad arguments");
-  {
-    std::vector<int64_t> last(S->walkers.size(), -1);
-    for (int64_t i = 0; i < n; ++i) {
-      if (walker[i] < 0 || walker[i] >= (int32_t)S->walkers.size()) return sfail(ABP_E_INVAL, "unknown walker id");
-      if (!(t_arrival[i] >= 0.0) || (i > 0 && t_arrival[i] < t_arrival[i - 1]))
-        return sfail(ABP_E_INVAL, "arrival times must be >= 0 and not decrease");
-      if (step[i] <= last[walker[i]]) return sfail(ABP_E_INVAL, "a walker's steps must be >= 0 and increase");
-      last[walker[i]] = step[i];
-    }
-  }
-  if (hipSetDevice(S->cv.device) != hipSuccess) return sfail(ABP_E_DEVICE, "cannot select device");
+abp_status abp_server_walker_atoms(abp_server* S, int32_t walker, int32_t* idx, int32_t* n) {
+  if (!S || !n) return sfail(ABP_E_INVAL, "NULL argument");
+  if (walker < 0 || walker >= (int32_t)S->walkers.size()) return sfail(ABP_E_INVAL, "unknown walker id");
+  const Walker& w = S->walkers[walker];
+  *n = w.n_cv;
+  if (idx) std::memcpy(idx, S->cv_atom.data() + w.cv_base, sizeof(int32_t) * (size_t)w.n_cv);
+  return ABP_OK;
+}
+
+abp_status abp_server_start(abp_server* S) {
+  if (!S) return sfail(ABP_E_INVAL, "NULL argument");
+  if (S->thread.joinable()) return sfail(ABP_E_INVAL, "the server is running");
+  if (S->walkers.empty()) return sfail(ABP_E_INVAL, "no walkers registered");
   if (abp::ctx_reserved(S->ctx) != abp_num_hills(S->ctx))
-    return sfail(ABP_E_INVAL, "reserved history slots are pending; commit them before a replay");
-  abp_status st = finalize(S);
-  if (st != ABP_OK) return st;
-  for (auto& sl : S->slots) {            // drain whatever an aborted replay left
+    return sfail(ABP_E_INVAL, "reserved history slots are pending; commit them before start");
+  if (hipSetDevice(S->cv.device) != hipSuccess) return sfail(ABP_E_DEVICE, "cannot select device");
+  if (!S->registered) {
+    const size_t nl = S->lidx.size();
+    if (hipMalloc(&S->d_lidx, sizeof(int32_t) * (nl + 1)) != hipSuccess ||
+        hipMalloc(&S->d_rx, sizeof(float) * (nl + 1)) != hipSuccess ||
+        hipMalloc(&S->d_ry, sizeof(float) * (nl + 1)) != hipSuccess ||
+        hipMalloc(&S->d_rz, sizeof(float) * (nl + 1)) != hipSuccess)
+      return sfail(ABP_E_NOMEM, "cannot allocate the CV lists");
+    if (nl) {
+      SRV_TRY(hipMemcpy(S->d_lidx, S->lidx.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice));
+      SRV_TRY(hipMemcpy(S->d_rx, S->lrx.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
+      SRV_TRY(hipMemcpy(S->d_ry, S->lry.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
+      SRV_TRY(hipMemcpy(S->d_rz, S->lrz.data(), sizeof(float) * nl, hipMemcpyHostToDevice));
+    }
+    S->registered = true;
+  }
+  for (auto& sl : S->slots) {
     SRV_TRY(hipStreamSynchronize(sl.stream));
     sl.busy = false;
   }
-  st = size_descriptors(S);
+  abp_status st = size_buffers(S);
   if (st != ABP_OK) return st;
-  S->launch_order.clear();
+  st = warm_up(S);
+  if (st != ABP_OK) return st;
+  st = abp_sync(S->ctx, nullptr);
+  if (st != ABP_OK) return st;
   reset_residency(S);
+  S->launch_order.clear();
   S->dep_done.clear();
-  const int64_t pool = S->pool_atoms;
-  const abp_server_stats keep{};
-  S->stats = keep;
-  S->stats.pool_atoms = pool;
-  const int ncv = S->ncv;
-  const auto t0 = std::chrono::steady_clock::now();
-  int64_t next = 0, completed = 0;
-
-  double last_progress = 0.0;
-  int64_t progress_mark = -1;
-  while (completed < n) {
-    const double t = now_s(t0);
-    // The loop always progresses (see admit); a stall means a broken invariant.
-    const int64_t mark = next + completed + S->stats.batches;
-    if (mark != progress_mark) {
-      progress_mark = mark;
-      last_progress = t;
-    } else if (t - last_progress > 60.0 && (next == n || t_arrival[next] < t - 60.0)) {
-      for (auto& sl : S->slots) (void)hipStreamSynchronize(sl.stream);
-      return sfail(ABP_E_DEVICE, "serving loop made no progress for 60 s");
-    }
-    // 1. arrivals
-    while (next < n && t_arrival[next] <= t) {
-      const int32_t wid = walker[next];
-      Walker& w = S->walkers[wid];
-      w.queue.push_back(next);
-      if (w.atom_base < 0) {
-        if (!w.waiting_admission) {
-          w.waiting_admission = true;
-          S->admission.push_back(wid);
-        }
-      } else {
-        make_ready(S, wid);
-      }
-      ++next;
-    }
-    // 2. retire finished batches, in launch order
-    while (!S->launch_order.empty()) {
-      Slot& sl = S->slots[S->launch_order.front()];
-      const hipError_t q = hipEventQuery(sl.done);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) return sfail(ABP_E_DEVICE, std::string("batch failed: ") + hipGetErrorString(q));
-      const double td = now_s(t0);
-      const int64_t nb = sl.nb;
-      for (int64_t j = 0; j < nb; ++j) {
-        const int64_t r = sl.reqs[j];
-        if (t_done) t_done[r] = td;
-        if (version) version[r] = sl.version;
-        if (deposit_slot) deposit_slot[r] = sl.dep_slots[j];
-        for (int a = 0; a < ncv; ++a) {
-          if (s_out) s_out[a * n + r] = sl.h_out[a * nb + j];
-          if (dV_out) dV_out[a * n + r] = sl.h_out[(ncv + 1 + a) * nb + j];
-        }
-        if (V_out) V_out[r] = sl.h_out[ncv * nb + j];
-        const int32_t wid = walker[r];
-        Walker& w = S->walkers[wid];
-        w.inflight = false;
-        if (w.queue.empty()) make_idle(S, wid);
-        else make_ready(S, wid);
-        if (sl.dep_slots[j] >= 0) S->dep_done[sl.dep_slots[j]] = true;
-      }
-      completed += nb;
-      S->stats.completed += nb;
-      sl.busy = false;
-      const int idx = S->launch_order.front();
-      S->launch_order.pop_front();
-      commit_prefix(S, S->slots[idx].stream);
-    }
-    // 3. admission
-    admit(S);
-    // 4. form and launch a batch on a free stream
-    if (S->ready.empty()) continue;
-    int free_slot = -1;
-    for (int k = 0; k < (int)S->slots.size(); ++k)
-      if (!S->slots[k].busy) { free_slot = k; break; }
-    if (free_slot < 0) continue;
-    Slot& sl = S->slots[free_slot];
-    const int64_t nb = std::min<int64_t>((int64_t)S->ready.size(), S->desc.max_batch);
-    DescLayout L(nb, S->nlists);
-    // Staging for the walkers admitted since their last batch (the buffers
-    // were sized for the worst case when the replay began).
-    {
-      int64_t n_stage = 0;
-      for (int64_t j = 0; j < nb; ++j) {
-        const Walker& w = S->walkers[S->ready[j]];
-        if (w.fresh) n_stage += w.entries;
-      }
-      if (L.total + (size_t)n_stage * sizeof(float4) > sl.desc_cap)
-        return sfail(ABP_E_DEVICE, "batch descriptor larger than sized (internal error)");
-    }
-    int64_t* d_atom_base = reinterpret_cast<int64_t*>(sl.h_desc + L.atom_base);
-    int64_t* d_stage_off = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
-    float4* h_stage = reinterpret_cast<float4*>(sl.h_desc + L.total);
-    int64_t spos = 0;
-    int64_t* d_step = reinterpret_cast<int64_t*>(sl.h_desc + L.step);
-    int64_t* d_dep = reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
-    double* d_hgt = reinterpret_cast<double*>(sl.h_desc + L.dep_height);
-    int32_t* d_n = reinterpret_cast<int32_t*>(sl.h_desc + L.n_atoms);
-    int32_t* d_wid = reinterpret_cast<int32_t*>(sl.h_desc + L.walker);
-    int32_t* d_lbeg = reinterpret_cast<int32_t*>(sl.h_desc + L.list_beg);
-    int32_t* d_llen = reinterpret_cast<int32_t*>(sl.h_desc + L.list_len);
-    sl.reqs.clear();
-    sl.dep_slots.clear();
-    sl.version = abp_num_hills(S->ctx);
-    bool any_deposit = false;
-    for (int64_t j = 0; j < nb; ++j) {
-      const int32_t wid = S->ready.front();
-      S->ready.pop_front();
-      Walker& w = S->walkers[wid];
-      w.in_ready = false;
-      w.inflight = true;
-      const int64_t r = w.queue.front();
-      w.queue.pop_front();
-      sl.reqs.push_back(r);
-      d_atom_base[j] = w.atom_base;
-      d_stage_off[j] = -1;
-      if (w.fresh) {          // this walker's CV entries, in list order
-        d_stage_off[j] = spos;
-        std::memcpy(h_stage + spos, S->himg.data() + w.img_base, sizeof(float4) * (size_t)w.entries);
-        spos += w.entries;
-        w.fresh = false;
-      }
-      d_step[j] = step[r];
-      d_n[j] = w.n;
-      d_wid[j] = wid;
-      int64_t lpos = w.list_base;
-      for (int q = 0; q < S->nlists; ++q) {
-        d_lbeg[q * nb + j] = (int32_t)lpos;
-        d_llen[q * nb + j] = w.len[q];
-        lpos += w.len[q];
-      }
-      int64_t slot = -1;
-      if (S->desc.deposit_every > 0 && step[r] > 0 && step[r] % S->desc.deposit_every == 0) {
-        if (abp_reserve(S->ctx, 1, &slot) != ABP_OK) slot = -1;     // history full: no deposit
-        if (slot >= 0) {
-          S->dep_done[slot] = false;
-          any_deposit = true;
-        }
-      }
-      d_dep[j] = slot;
-      d_hgt[j] = S->desc.height_decay > 0 ? S->desc.height0 * std::exp(-(double)std::max<int64_t>(slot, 0) /
-                                                                        S->desc.height_decay)
-                                          : S->desc.height0;
-      sl.dep_slots.push_back(slot);
-    }
-    sl.nb = nb;
-    // Workspace for this batch's partial sums (split or chained shape); grows with the history
-    // (the slot is idle here, so freeing its old buffer is safe).
-    const size_t need = abp::force_uses_workspace(nb, sl.version, 0, 0)
-                            ? abp::force_workspace_bytes(nb, abp::force_blocks_per_walker(sl.version, 0, 0), ncv)
-                            : 0;
-    if (need > sl.ws_bytes) {
-      if (sl.d_ws) SRV_TRY(hipFree(sl.d_ws));
-      sl.d_ws = nullptr;
-      sl.ws_bytes = 0;
-      const size_t want = std::max(need, abp::force_workspace_bytes(
-          S->desc.max_batch, abp::force_blocks_per_walker(2 * sl.version + 4096, 0, 0), ncv));
-      if (hipMalloc(&sl.d_ws, want) != hipSuccess) return sfail(ABP_E_NOMEM, "cannot grow the batch workspace");
-      SRV_TRY(hipMemset(sl.d_ws, 0, want));
-      sl.ws_bytes = want;
-    }
-    SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float4), hipMemcpyHostToDevice,
-                           sl.stream));
-    abp::EngineArgs E;
-    E.nb = nb;
-    E.atom_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.atom_base);
-    E.n_atoms = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_atoms);
-    E.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
-    E.stage = reinterpret_cast<const float4*>(sl.d_desc + L.total);
-    E.walker = reinterpret_cast<const int32_t*>(sl.d_desc + L.walker);
-    E.step = reinterpret_cast<const int64_t*>(sl.d_desc + L.step);
-    E.nlists = S->nlists;
-    E.list_beg = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_beg);
-    E.list_len = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_len);
-    E.list_idx = S->d_lidx;
-    E.amplitude = S->desc.amplitude;
-    E.x = pool_array(S, 0);
-    E.y = pool_array(S, 1);
-    E.z = pool_array(S, 2);
-    E.mass = pool_array(S, 3);
-    E.fx = pool_array(S, 4);
-    E.fy = pool_array(S, 5);
-    E.fz = pool_array(S, 6);
-    E.x0 = pool_array(S, 7);
-    E.y0 = pool_array(S, 8);
-    E.z0 = pool_array(S, 9);
-    SRV_TRY(abp::launch_engine_step(E, sl.stream));
-    abp::ForceArgs A;
-    std::memset(&A, 0, sizeof(A));
-    A.ncv = ncv;
-    for (int a = 0; a < 3; ++a) A.kind[a] = S->kind[a];
-    A.list_beg = E.list_beg;
-    A.list_len = E.list_len;
-    A.list_idx = S->d_lidx;
-    A.ref_x = S->d_rx;
-    A.ref_y = S->d_ry;
-    A.ref_z = S->d_rz;
-    A.nw = nb;
-    A.atom_base = E.atom_base;
-    A.n_atoms = E.n_atoms;
-    A.x = E.x;
-    A.y = E.y;
-    A.z = E.z;
-    A.mass = E.mass;
-    A.fx = E.fx;
-    A.fy = E.fy;
-    A.fz = E.fz;
-    A.n_visible = nullptr;
-    A.n_visible_default = sl.version;
-    A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(sl.d_desc + L.dep_slot) : nullptr;
-    A.deposit_height = reinterpret_cast<const double*>(sl.d_desc + L.dep_height);
-    A.s = sl.m_out;
-    A.V = sl.m_out + ncv * nb;
-    A.dVds = sl.m_out + (ncv + 1) * nb;
-    A.prec = S->desc.prec;
-    A.err = S->cv.err;
-    SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
-    SRV_TRY(hipEventRecord(sl.done, sl.stream));
-    sl.busy = true;
-    S->launch_order.push_back(free_slot);
-    S->stats.batches++;
-    if (nb > S->stats.max_batch_seen) S->stats.max_batch_seen = nb;
+  {
+    std::lock_guard<std::mutex> lk(S->mu_out);
+    S->completed.clear();
   }
-  for (auto& sl : S->slots) SRV_TRY(hipStreamSynchronize(sl.stream));
-  S->stats.wall_seconds = now_s(t0);
-  // Device-side flags (invalid walker, non-finite input) surface here.
-  return abp_sync(S->ctx, nullptr);
+  {
+    std::lock_guard<std::mutex> lk(S->mu_in);
+    S->incoming.clear();
+    S->next_id = 0;
+  }
+  S->outstanding = 0;
+  {
+    std::lock_guard<std::mutex> lk(S->mu_stats);
+    const int64_t pool = S->pool_atoms;
+    S->stats = abp_server_stats{};
+    S->stats.pool_atoms = pool;
+    S->trace.clear();
+    S->trace_next = 0;
+    S->t_start = now_s(S);
+    S->t_stop = -1.0;
+  }
+  S->thread_status = ABP_OK;
+  S->thread_error.clear();
+  S->stopping = false;
+  S->running = true;
+  try {
+    S->thread = std::thread(scheduler, S);
+  } catch (...) {
+    S->running = false;
+    return sfail(ABP_E_NOMEM, "cannot start the scheduler thread");
+  }
+  return ABP_OK;
+}
+
+abp_status abp_server_submit(abp_server* S, int32_t walker, int64_t step, const float* xyz, float* force_out,
+                             int64_t* request_id) {
+  if (!S || !xyz) return sfail(ABP_E_INVAL, "NULL argument");
+  if (!S->running.load() || S->stopping.load()) return sfail(ABP_E_INVAL, "the server is not running");
+  if (walker < 0 || walker >= (int32_t)S->walkers.size()) return sfail(ABP_E_INVAL, "unknown walker id");
+  const int32_t n = S->walkers[walker].n_cv;
+  for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
+    if (!std::isfinite(xyz[i])) return sfail(ABP_E_NONFINITE, "non-finite CV-atom coordinate");
+  int32_t r;
+  int64_t id;
+  {
+    std::lock_guard<std::mutex> lk(S->mu_in);
+    if (S->free_records.empty()) return sfail(ABP_E_BUSY, "max_pending requests are outstanding; poll first");
+    r = S->free_records.back();
+    S->free_records.pop_back();
+    id = S->next_id++;
+  }
+  Record& R = S->records[r];
+  std::memcpy(S->arena + R.arena_off, xyz, sizeof(float) * 3 * (size_t)n);
+  R.id = id;
+  R.walker = walker;
+  R.n_cv = n;
+  R.step = step;
+  R.force_out = force_out;
+  R.t_submit = now_s(S);
+  R.dep_slot = -1;
+  S->outstanding.fetch_add(1);
+  {
+    std::lock_guard<std::mutex> lk(S->mu_in);
+    S->incoming.push_back(r);
+  }
+  S->cv_in.notify_one();
+  {
+    std::lock_guard<std::mutex> lk(S->mu_stats);
+    S->stats.submitted++;
+  }
+  if (request_id) *request_id = id;
+  return ABP_OK;
+}
+
+abp_status abp_server_poll(abp_server* S, abp_server_result* out, int64_t max, int64_t* n, int64_t wait_us) {
+  if (!S || !n || (max > 0 && !out) || max < 0) return sfail(ABP_E_INVAL, "bad arguments");
+  *n = 0;
+  std::vector<int32_t> take;
+  {
+    std::unique_lock<std::mutex> lk(S->mu_out);
+    if (S->completed.empty() && wait_us > 0)
+      S->cv_out.wait_for(lk, std::chrono::microseconds(wait_us),
+                         [S] { return !S->completed.empty() || !S->running.load(); });
+    while (!S->completed.empty() && (int64_t)take.size() < max) {
+      take.push_back(S->completed.front());
+      S->completed.pop_front();
+    }
+  }
+  for (size_t k = 0; k < take.size(); ++k) {
+    const Record& R = S->records[take[k]];
+    abp_server_result& o = out[k];
+    o.request = R.id;
+    o.step = R.step;
+    o.version = R.version;
+    o.deposit_slot = R.dep_slot;
+    o.walker = R.walker;
+    o.n_cv_atoms = R.n_cv;
+    o.t_submit = R.t_submit;
+    o.t_done = R.t_done;
+    for (int a = 0; a < 3; ++a) {
+      o.s[a] = a < S->ncv ? R.s[a] : 0.0;
+      o.dVds[a] = a < S->ncv ? R.dV[a] : 0.0;
+    }
+    o.V = R.V;
+    if (R.force_out)
+      std::memcpy(R.force_out, S->arena + R.arena_off + 3 * (int64_t)R.n_cv, sizeof(float) * 3 * (size_t)R.n_cv);
+  }
+  if (!take.empty()) {
+    std::lock_guard<std::mutex> lk(S->mu_in);
+    for (const int32_t r : take) S->free_records.push_back(r);
+  }
+  *n = (int64_t)take.size();
+  return ABP_OK;
 }
 
 abp_status abp_server_get_stats(abp_server* S, abp_server_stats* out) {
   if (!S || !out) return sfail(ABP_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu_stats);
   *out = S->stats;
+  out->wall_seconds = (S->t_stop >= 0.0 ? S->t_stop : now_s(S)) - S->t_start;
+  return ABP_OK;
+}
+
+abp_status abp_server_trace(abp_server* S, abp_server_batch* out, int64_t max, int64_t* n) {
+  if (!S || !n || max < 0 || (max > 0 && !out)) return sfail(ABP_E_INVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(S->mu_stats);
+  const size_t have = S->trace.size();
+  const size_t take = std::min(have, (size_t)max);
+  // oldest first among the last `take` records
+  const size_t first = S->trace_next - take;
+  for (size_t k = 0; k < take; ++k) {
+    const size_t i = first + k;
+    out[k] = have < kTraceMax ? S->trace[i] : S->trace[i % kTraceMax];
+  }
+  *n = (int64_t)take;
   return ABP_OK;
 }
 

@@ -46,10 +46,10 @@ def _clean_run(lib, ctx, wk):
 
 
 @pytest.mark.parametrize("shape", ["fused", "split", "chain"])
-def test_bad_atom_index_isolated(lib, small, shape, monkeypatch):
+def test_bad_atom_index_isolated(lib, small, shape):
     wk, spec, hills = small
-    monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
     ctx = _ctx(lib, spec, hills)
+    lib.abp_set_force_shape(ctx, shape)
     s0, V0, dV0, fx0 = _clean_run(lib, ctx, wk)
     bad = W.Walkers(**{**wk.__dict__, "list_idx": wk.list_idx.copy()})
     e = int(wk.list_off[1, 0, 3])                      # walker 3's first torsion atom

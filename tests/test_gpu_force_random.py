@@ -110,7 +110,7 @@ def _check_forces(wk, dw, ref, scale_cv, gabs, tol):
 
 
 @pytest.mark.parametrize("seed", range(36))
-def test_random_bias_force(seed, monkeypatch):
+def test_random_bias_force(seed):
     device()
     from paper_1609_09833_amd import abp
     spec, hills, wk, shape, prec = _case(seed)
@@ -118,7 +118,7 @@ def test_random_bias_force(seed, monkeypatch):
     if hills.n:
         abp.bias_deposit(ctx, to_dev(hills.centers), to_dev(hills.heights))
     if shape != "grid":
-        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+        abp.abp_set_force_shape(ctx, shape)
     dw = abp.DeviceWalkers(wk)
     mode = abp.ABP_EVAL_GRID if shape == "grid" else abp.ABP_EVAL_DIRECT
     s, V, dV = abp.bias_force(ctx, dw, mode=mode, prec=prec)

@@ -23,13 +23,13 @@ def lib():
 
 @pytest.mark.parametrize("n_hills,shape", [(3000, None), (20000, None), (20000, "chain")])   # fused, split, chained
 @pytest.mark.parametrize("mode", ["direct", "grid"])
-def test_bias_force_graph_replays(lib, n_hills, shape, mode, monkeypatch):
+def test_bias_force_graph_replays(lib, n_hills, shape, mode):
     import torch
-    if shape:
-        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)     # its counters must be back at zero after every replay
     wk = W.ligand_pocket_walkers(seed=71, n_walkers=64, atoms_lo=1000, atoms_hi=3000)
     spec, hills = W.ligand_pocket_hills(seed=72, n_hills=n_hills)
     ctx = lib.Context(spec, hills.n)
+    if shape:
+        lib.abp_set_force_shape(ctx, shape)      # the chained launch's counters must be back at zero after every replay
     lib.bias_deposit(ctx, torch.tensor(hills.centers, device="cuda"), torch.tensor(hills.heights, device="cuda"))
     dw = lib.DeviceWalkers(wk)
     m = lib.ABP_EVAL_GRID if mode == "grid" else lib.ABP_EVAL_DIRECT

@@ -385,7 +385,7 @@ SHAPE_CASES = [(W.KERNEL_GAUSS, W.TRANSFORM_PLAIN, KAHAN), (W.KERNEL_GAUSS, W.TR
 
 
 @pytest.mark.parametrize("kernel,transform,prec", SHAPE_CASES)
-def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, monkeypatch):
+def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec):
     import dataclasses
     wk = shape_walkers
     spec, hills = W.ligand_pocket_hills(seed=22, n_hills=40000)
@@ -397,7 +397,7 @@ def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, mo
     nvis = rng.integers(0, hills.n + 1, wk.nw)
     nvis[:6] = [0, 1, 63, 64, 65, hills.n]                # chunk boundaries of the decomposition
     # fused: 256 walkers in one launch
-    monkeypatch.setenv("ABP_FORCE_SHAPE", "fused")
+    abp.abp_set_force_shape(ctx, "fused")
     dw = abp.DeviceWalkers(wk)
     s, V, dV = abp.bias_force(ctx, dw, prec=prec, n_visible=nvis)
     abp.abp_sync(ctx)
@@ -420,7 +420,7 @@ def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, mo
     assert V[0] == 0.0 and np.all(dV[:, 0] == 0.0)        # no visible hills
     # split and chained: a 64-walker batch (mixed partial counts in a wave) and single walkers
     for shape in ("split", "chain"):
-        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+        abp.abp_set_force_shape(ctx, shape)
         d64 = abp.DeviceWalkers(_first_walkers(wk, 64))
         s64, V64, dV64 = abp.bias_force(ctx, d64, prec=prec, n_visible=nvis[:64])
         assert np.array_equal(host(s64), s[:, :64]), shape
@@ -436,7 +436,7 @@ def test_fused_and_split_shapes_agree(shape_walkers, kernel, transform, prec, mo
             assert np.array_equal(host(dV1)[:, 0], dV[:, w]), shape
             b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
             assert np.array_equal(host(d1.fy), F[1][b:b + n]), shape
-    monkeypatch.delenv("ABP_FORCE_SHAPE")
+    abp.abp_set_force_shape(ctx, "auto")
     d2 = abp.DeviceWalkers(W.single_walker(wk, 3))           # the default shape for this history
     s2, V2, _ = abp.bias_force(ctx, d2, prec=prec, n_visible=nvis[3:4])
     assert np.array_equal(host(V2)[0], V[3])
@@ -542,7 +542,7 @@ GENERAL_CASES = [
 
 @pytest.mark.parametrize("name,seed,nw,n_atoms,na,nb,shared,kinds", GENERAL_CASES)
 @pytest.mark.parametrize("shape", ["fused", "split", "grid"])
-def test_general_chain_rule_paths(name, seed, nw, n_atoms, na, nb, shared, kinds, shape, monkeypatch):
+def test_general_chain_rule_paths(name, seed, nw, n_atoms, na, nb, shared, kinds, shape):
     device()
     wk = _general_walkers(seed, nw, n_atoms, na, nb, shared, kinds)
     rng = np.random.default_rng(seed + 100)
@@ -555,7 +555,7 @@ def test_general_chain_rule_paths(name, seed, nw, n_atoms, na, nb, shared, kinds
     hills = W.Hills(cen, rng.uniform(0.1, 1.2, 3000))
     ctx = make_ctx(spec, hills)
     if shape != "grid":
-        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
+        abp.abp_set_force_shape(ctx, shape)
     dw = abp.DeviceWalkers(wk)
     mode = abp.ABP_EVAL_GRID if shape == "grid" else abp.ABP_EVAL_DIRECT
     s, V, dV = abp.bias_force(ctx, dw, mode=mode)
@@ -812,8 +812,8 @@ def test_wt_deposit_same_in_every_shape(monkeypatch):
     spec = dataclasses.replace(spec, wt_dT=3.0)
     got = []
     for shape in ("fused", "split", "chain"):
-        monkeypatch.setenv("ABP_FORCE_SHAPE", shape)
         ctx = make_ctx(spec, hills, capacity=hills.n + wk.nw)
+        abp.abp_set_force_shape(ctx, shape)
         first = abp.abp_reserve(ctx, wk.nw)
         slots = first + np.arange(wk.nw)
         dw = abp.DeviceWalkers(wk)

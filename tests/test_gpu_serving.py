@@ -1,18 +1,24 @@
 """GPU tests of the serving loop (abp_server_*): continuous batching of
 bias-force requests from many walkers sharing one hill history.
 
-Every request is re-evaluated by the oracle on the host: the walker's
-positions at that step are reproduced bit for bit from the synthetic engine's
-hash, the hills it saw are the first `version` hills of the exported history,
-and s, V and dV/ds must agree to the same bounds as a direct bias_force call.
-Deposits must land in the slots they report, with the reported CV value as
-center and the height law's height.
+A request carries the positions of a walker's CV atoms for one MD step and
+returns the bias force on them (the per-step exchange of the paper's
+"Minimization of Interprocess Communications"). Every request is re-evaluated
+by the oracle on the host at the history version it saw (the first `version`
+hills of the exported history), with the positions that were submitted: s,
+V, dV/ds and the force on every CV atom must agree to the same bounds as a
+direct bias_force call. Deposits must land in the slots they report, with the
+reported CV value as centre and the height law's height, and the grid the
+commits built must equal the oracle's grid of the final history.
 """
+import threading
+import time
+
 import numpy as np
 import pytest
 
 from paper_1609_09833_amd import workloads as W
-from tests.gpu_common import device
+from tests.gpu_common import device, cv_atom_grad_abs
 from tests.tolerance import check_bound
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +29,12 @@ def lib():
     device()
     from paper_1609_09833_amd import abp as _abp
     return _abp
+
+
+@pytest.fixture(scope="module")
+def drv(lib):
+    from paper_1609_09833_amd.examples import serve_driver
+    return serve_driver
 
 
 AMP = 2.0 ** -7          # nm, exact in float32
@@ -42,52 +54,97 @@ def _setup(lib, n_hills=N_HILLS, capacity_extra=4096):
 
 
 def _register(srv, wk):
-    ids = []
+    ids, ncv = [], []
     for w in range(wk.nw):
         b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
         lens, idx, rx, ry, rz = W.walker_lists(wk, w)
-        ids.append(srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx,
-                                  rx, ry, rz))
+        wid, nc = srv.add_walker(wk.mass[b:b + n], lens, idx, rx, ry, rz)
+        ids.append(wid)
+        ncv.append(nc)
+        atoms = srv.walker_atoms(wid)
+        assert np.array_equal(atoms, np.unique(idx)) and nc == atoms.size
     assert ids == list(range(wk.nw))
+    return np.array(ncv)
 
 
-def _oracle_request(spec, centers, heights, wk, w, step, version):
+def _cv_budget(lib, ncv, fraction):
+    return lib.ABP_SERVER_BYTES_PER_ATOM * int(ncv.astype(np.int64).sum() * fraction)
+
+
+def _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version):
+    """The oracle's bias force for walker w with its CV atoms at xyz ([3][n_cv]),
+    over the first `version` hills: (s, V, dV, forces on the CV atoms [3][n_cv],
+    A0, A, per-atom force scale [3][n_cv])."""
     from oracle import bias_eval, bias_force
     b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
-    lens, idx, _, _, _ = W.walker_lists(wk, w)
-    x, y, z = W.engine_positions(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], w, step, idx, AMP)
+    x, y, z = (np.asarray(a[b:b + n], dtype=np.float32).copy() for a in (wk.x, wk.y, wk.z))
+    k = atoms.size
+    x[atoms], y[atoms], z[atoms] = xyz[:k], xyz[k:2 * k], xyz[2 * k:3 * k]
     one = W.single_walker(wk, w, x, y, z)
     zero = np.zeros(n)
     c, h = centers[:, :version], heights[:version]
-    s, V, dV, _, _, _, status = bias_force(spec, c, h, one, zero, zero, zero)
+    s, V, dV, fx, fy, fz, status = bias_force(spec, c, h, one, zero, zero, zero)
     assert status[0] == 0
     _, _, sA0, sA = bias_eval(spec, c, h, s)
-    return s[:, 0], V[0], dV[:, 0], sA0[0], sA[:, 0]
+    F = np.stack([fx[atoms], fy[atoms], fz[atoms]])
+    gabs = cv_atom_grad_abs(one, s)
+    scale = np.zeros((3, k))
+    for j, at in enumerate(atoms):
+        g = gabs[int(at)]                                  # [ncv, 3]
+        for a in range(wk.ncv):
+            scale[:, j] += np.maximum(np.abs(dV[a, 0]), sA[a, 0]) * g[a]
+    return s[:, 0], V[0], dV[:, 0], F, sA0[0], sA[:, 0], scale
 
 
 def _wrap(d):
     return (d + np.pi) % (2 * np.pi) - np.pi
 
 
-def test_serving_with_deposits_matches_oracle(lib):
-    """Batched, evicting, depositing replay: every request checked against the oracle."""
+def _check_request(name, spec, centers, heights, wk, srv, r, w, xyz, version, s, V, dV, F):
+    atoms = srv.walker_atoms(w)
+    s_o, V_o, dV_o, F_o, A0, A, fscale = _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version)
+    ds = s - s_o
+    for a in range(spec.ndim):
+        if spec.periodic[a]:
+            ds[a] = _wrap(ds[a])
+    assert np.abs(ds).max() < 1e-12, (name, r, ds)
+    rv = check_bound(f"{name} V (request {r})", np.array([V]), np.array([V_o]), np.array([A0]))
+    rg = check_bound(f"{name} dV/ds (request {r})", dV, dV_o, A)
+    # forces are FP32: at least their output rounding
+    rf = check_bound(f"{name} forces (request {r})", F.reshape(3, -1), F_o, fscale, tol=1e-5, floor=0.0)
+    return max(rv, rg, rf)
+
+
+def test_serving_with_deposits_matches_oracle(lib, drv):
+    """Batched, evicting, depositing replay through submit/poll: every request's
+    s, V, dV/ds and forces against the oracle, deposits in order, and the grid
+    built by the commits (on two streams) equal to the oracle's."""
+    import oracle
     spec, hills, wk, ctx = _setup(lib)
-    # about a third of the walkers fit
-    budget = lib.ABP_SERVER_BYTES_PER_ATOM * int(wk.n_atoms.astype(np.int64).sum() // 3)
-    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=16, streams=2, deposit_every=3,
-                     height0=1.2, height_decay=20000.0, amplitude=AMP)
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 20, max_batch=16, streams=2, deposit_every=3,
+                     height0=1.2, height_decay=20000.0, max_pending=256)
+    ncv = _register(srv, wk)
+    srv.close()
+    # about a third of the walkers' CV atoms fit
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=_cv_budget(lib, ncv, 1 / 3), max_batch=16, streams=2,
+                     deposit_every=3, height0=1.2, height_decay=20000.0, max_pending=256)
     _register(srv, wk)
-    # 120 ms of arrivals: walkers go idle between their requests, so they are evicted and
-    # admitted again even if the first launches of the process (code loading) stall the loop
+    eng = drv.Engines(srv, wk)
+    srv.start()
+    # 120 ms of arrivals: walkers go idle between their requests, so they are evicted and admitted again
     t, w, step = W.serving_requests(seed=1, n_walkers=N_WALKERS, rate=5_000.0, n_requests=600)
-    print(f"serving replay: {len(t)} requests, {N_WALKERS} walkers, budget {budget} B", flush=True)
-    out = srv.replay(w, step, t)
-    st = out["stats"]
+    print(f"serving replay: {len(t)} requests, {N_WALKERS} walkers", flush=True)
+    out = drv.replay(srv, eng, w, step, t, AMP)
+    srv.stop()
+    st = srv.stats()
     n = len(t)
-    assert st["completed"] == n
+    assert st["completed"] == n == st["submitted"]
     assert st["evictions"] > 0 and st["admissions"] > N_WALKERS
     assert st["max_batch_seen"] <= 16 and st["batches"] >= n // 16
-    assert np.all(np.isfinite(out["t_done"])) and np.all(out["t_done"] >= t)
+    assert np.all(np.isfinite(out["t_done"])) and np.all(out["t_done"] >= out["t_submit"])
+    tr = srv.trace()
+    assert tr.size == st["batches"] and tr["requests"].sum() == n
+    assert np.all(tr["t_formed"] <= tr["t_launched"]) and np.all(tr["t_launched"] <= tr["t_done"])
     # deposits: one per request whose step is a positive multiple of 3, slots dense after the seed hills
     dep = out["deposit_slot"]
     want_dep = (step % 3) == 0
@@ -104,46 +161,125 @@ def test_serving_with_deposits_matches_oracle(lib):
         assert np.all(np.diff(v) >= 0)
     centers, heights = lib.abp_hills_export(ctx)
     assert np.array_equal(centers[:, :N_HILLS], hills.centers)
-    # each deposited hill holds the depositing request's CV value and the height law's height
     for r in np.flatnonzero(dep >= 0):
         k = int(dep[r])
         assert np.array_equal(centers[:, k], out["s"][:, r])
         assert abs(heights[k] - 1.2 * np.exp(-k / 20000.0)) <= 1e-15 * heights[k]
-    # oracle re-evaluation of every request
-    s_g, V_g, dV_g = out["s"], out["V"], out["dVds"]
-    s_o = np.zeros_like(s_g); V_o = np.zeros_like(V_g); dV_o = np.zeros_like(dV_g)
-    A0 = np.zeros(n); A = np.zeros((wk.ncv, n))
+    # every request against the oracle, forces included
+    worst = 0.0
     for r in range(n):
-        s_o[:, r], V_o[r], dV_o[:, r], A0[r], A[:, r] = _oracle_request(
-            spec, centers, heights, wk, int(w[r]), int(step[r]), int(ver[r]))
-    assert np.abs(s_g[0] - s_o[0]).max() < 1e-12
-    assert np.abs(_wrap(s_g[1] - s_o[1])).max() < 1e-12
-    check_bound("served V", V_g, V_o, A0)
-    check_bound("served dVds", dV_g, dV_o, A)
+        o, k3 = int(out["offset"][r]), 3 * int(eng.n_cv[w[r]])
+        worst = max(worst, _check_request("served", spec, centers, heights, wk, srv, r, int(w[r]),
+                                          out["positions"][o:o + k3], int(ver[r]), out["s"][:, r], out["V"][r],
+                                          out["dVds"][:, r], out["forces"][o:o + k3]))
+    print(f"served requests: worst error / bound {worst:.3e}")
+    # the grid the serial commits built equals the oracle's grid of the final history
+    H = lib.abp_grid_export(ctx)
+    Ho = oracle.grid_all(spec, centers, heights)
+    np.testing.assert_allclose(H, Ho, rtol=1e-9, atol=1e-12 * np.abs(Ho).max())
     srv.close()
     ctx.close()
 
 
-def test_serving_alone_equals_in_the_mix(lib):
-    """Without deposits a request's result is bitwise the same whether it ran
-    alone (one request per launch, one stream) or inside mixed batches."""
+def test_serving_alone_equals_in_the_mix(lib, drv):
+    """Without deposits a request's s, V, dV/ds and forces are bitwise the same
+    whether it ran alone (one request per launch, one stream) or inside mixed
+    batches on three streams."""
     spec, hills, wk, ctx = _setup(lib)
     t, w, step = W.serving_requests(seed=2, n_walkers=N_WALKERS, rate=100_000.0, n_requests=400)
     res = []
     for mb, ns in ((1, 1), (64, 3)):
-        srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=mb, streams=ns, deposit_every=0,
-                         amplitude=AMP)
+        srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=mb, streams=ns, deposit_every=0)
         _register(srv, wk)
+        eng = drv.Engines(srv, wk)
+        srv.start()
         print(f"replay max_batch={mb} streams={ns}", flush=True)
-        res.append(srv.replay(w, step, t))
+        out = drv.replay(srv, eng, w, step, t, AMP)
+        srv.stop()
+        out["stats"] = srv.stats()
+        res.append(out)
         srv.close()
     alone, mix = res
     assert alone["stats"]["max_batch_seen"] == 1
     assert mix["stats"]["batches"] < alone["stats"]["batches"]
-    for k in ("s", "V", "dVds"):
+    for k in ("s", "V", "dVds", "forces", "positions"):
         assert np.array_equal(alone[k], mix[k]), k
+    assert np.all(np.isfinite(alone["forces"]))
     assert np.all(alone["version"] == N_HILLS) and np.all(mix["version"] == N_HILLS)
     assert np.all(alone["deposit_slot"] == -1)
+    ctx.close()
+
+
+def test_serving_live_submit_and_poll(lib):
+    """Engines in host threads submit each step's CV-atom positions as it
+    arrives and a poller collects results while others are on the GPU; every
+    result, forces included, against the oracle."""
+    spec, hills, wk, ctx = _setup(lib)
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=8, streams=2, deposit_every=5,
+                     height0=1.0, max_pending=64)
+    ncv = _register(srv, wk)
+    srv.start()
+    rng = np.random.default_rng(9)
+    n_threads, per_thread = 4, 40
+    sent = {}                                      # request id -> (walker, step, xyz, force_out)
+    lock = threading.Lock()
+    errors = []
+
+    def engine(tid):
+        try:
+            walkers = list(range(tid, wk.nw, n_threads))
+            steps = {wi: 1 for wi in walkers}
+            for k in range(per_thread):
+                wi = walkers[k % len(walkers)]
+                atoms = srv.walker_atoms(wi)
+                b = int(wk.atom_base[wi])
+                base = np.concatenate([wk.x[b + atoms], wk.y[b + atoms], wk.z[b + atoms]]).astype(np.float32)
+                xyz = base + np.float32(AMP) * rng_local[tid].uniform(-1, 1, base.size).astype(np.float32)
+                fo = np.full(base.size, np.nan, dtype=np.float32)
+                while True:
+                    try:
+                        rid = srv.submit(wi, steps[wi], xyz, fo)
+                        break
+                    except lib.AbpError as e:
+                        if e.status != lib.ABP_E_BUSY:
+                            raise
+                        time.sleep(1e-4)
+                with lock:
+                    sent[rid] = (wi, steps[wi], xyz, fo)
+                steps[wi] += 1
+                time.sleep(float(rng_local[tid].exponential(2e-4)))
+        except Exception as e:                     # surfaced by the main thread
+            errors.append(e)
+
+    rng_local = [np.random.default_rng(100 + i) for i in range(n_threads)]
+    threads = [threading.Thread(target=engine, args=(i,)) for i in range(n_threads)]
+    for th in threads:
+        th.start()
+    got = []
+    total = n_threads * per_thread
+    deadline = time.time() + 60
+    while len(got) < total and time.time() < deadline and not errors:
+        res = srv.poll(256, wait_us=2000)
+        got.extend(res.tolist())
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    srv.stop()
+    got.extend(srv.poll(4096).tolist())
+    assert len(got) == total
+    names = lib.SERVER_RESULT.names
+    centers, heights = lib.abp_hills_export(ctx)
+    worst = 0.0
+    for row in got:
+        r = dict(zip(names, row))
+        wi, stp, xyz, fo = sent[r["request"]]
+        assert r["walker"] == wi and r["step"] == stp and r["n_cv_atoms"] == ncv[wi]
+        assert (r["deposit_slot"] >= 0) == (stp % 5 == 0)
+        worst = max(worst, _check_request("live", spec, centers, heights, wk, srv, r["request"], wi, xyz,
+                                          int(r["version"]), np.array(r["s"][:2]), r["V"], np.array(r["dVds"][:2]),
+                                          fo))
+    print(f"live requests: worst error / bound {worst:.3e}")
+    srv.close()
     ctx.close()
 
 
@@ -153,36 +289,59 @@ def test_serving_rejects_bad_input(lib):
         lib.Server(ctx, [W.CV_TORSION, W.CV_TORSION])         # torsion on a non-periodic axis
     with pytest.raises(lib.AbpError):
         lib.Server(ctx, wk.kinds, max_batch=0)
-    small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=lib.ABP_SERVER_BYTES_PER_ATOM * 1000)
+    with pytest.raises(lib.AbpError):
+        lib.Server(ctx, wk.kinds, max_pending=0)
+    small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=lib.ABP_SERVER_BYTES_PER_ATOM * 100)
     b, n = int(wk.atom_base[0]), int(wk.n_atoms[0])
     lens, idx, rx, ry, rz = W.walker_lists(wk, 0)
     with pytest.raises(lib.AbpError) as e:
-        small.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx)
+        small.add_walker(wk.mass[b:b + n], lens, idx)            # more CV atoms than the budget holds
     assert e.value.status == lib.ABP_E_NOMEM
-    srv = lib.Server(ctx, wk.kinds)
+    srv = lib.Server(ctx, wk.kinds, max_pending=2)
     bad = idx.copy()
     bad[0] = n                                                 # out of range
     with pytest.raises(lib.AbpError):
-        srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, bad)
-    wid = srv.add_walker(wk.x[b:b + n], wk.y[b:b + n], wk.z[b:b + n], wk.mass[b:b + n], lens, idx)
+        srv.add_walker(wk.mass[b:b + n], lens, bad)
     with pytest.raises(lib.AbpError):
-        srv.replay([wid, wid], [1, 2], [0.001, 0.0])           # arrivals out of order
+        srv.start()                                            # no walkers yet
+    wid, ncv = srv.add_walker(wk.mass[b:b + n], lens, idx)
+    xyz = np.zeros(3 * ncv, dtype=np.float32)
     with pytest.raises(lib.AbpError):
-        srv.replay([wid, wid], [2, 2], [0.0, 0.0])             # steps must increase
+        srv.submit(wid, 1, xyz)                                # not started
+    srv.start()
     with pytest.raises(lib.AbpError):
-        srv.replay([5], [1], [0.0])                            # unknown walker
-    out = srv.replay([wid], [1], [0.0])                        # still usable afterwards
-    assert out["stats"]["completed"] == 1
+        srv.add_walker(wk.mass[b:b + n], lens, idx)            # registration is closed
+    with pytest.raises(lib.AbpError):
+        srv.submit(5, 1, xyz)                                  # unknown walker
+    nan = xyz.copy()
+    nan[3] = np.nan
+    with pytest.raises(lib.AbpError) as e:
+        srv.submit(wid, 1, nan)
+    assert e.value.status == lib.ABP_E_NONFINITE
+    base = np.concatenate([wk.x[b + srv.walker_atoms(wid)], wk.y[b + srv.walker_atoms(wid)],
+                           wk.z[b + srv.walker_atoms(wid)]]).astype(np.float32)
+    srv.submit(wid, 1, base)
+    srv.submit(wid, 2, base)
+    with pytest.raises(lib.AbpError) as e:
+        srv.submit(wid, 3, base)                               # two outstanding until polled
+    assert e.value.status == lib.ABP_E_BUSY
+    got = []
+    while len(got) < 2:
+        got.extend(srv.poll(8, wait_us=100000).tolist())
+    srv.submit(wid, 3, base)                                   # room again
+    srv.stop()
+    assert len(srv.poll(8)) == 1
+    assert srv.stats()["completed"] == 3
     srv.close()
     small.close()
     ctx.close()
 
 
 @pytest.mark.parametrize("kinds", [(W.CV_TORSION,), (W.CV_COM_DIST, W.CV_TORSION, W.CV_RMSD_OFF)])
-def test_serving_one_and_three_cvs(lib, kinds):
+def test_serving_one_and_three_cvs(lib, drv, kinds):
     """The serving loop in 1-D and 3-D CV spaces (walkers of uneven size with
     a torsion; a COM distance, a torsion and an offset RMSD), with evictions
-    and deposits: every request against the oracle."""
+    and deposits: every request, forces included, against the oracle."""
     import torch
     from tests.test_gpu_force_random import _walkers
     rng = np.random.default_rng(77 + len(kinds))
@@ -199,24 +358,26 @@ def test_serving_one_and_three_cvs(lib, kinds):
     ctx = lib.Context(spec, nh + 1024)
     lib.bias_deposit(ctx, torch.tensor(cen, device="cuda"), torch.tensor(hts, device="cuda"))
     torch.cuda.synchronize()
-    budget = lib.ABP_SERVER_BYTES_PER_ATOM * int(wk.n_atoms.astype(np.int64).sum() // 3)
-    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=8, streams=2, deposit_every=4,
-                     height0=1.0, height_decay=10000.0, amplitude=AMP)
+    probe = lib.Server(ctx, wk.kinds)
+    ncv = _register(probe, wk)
+    probe.close()
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=_cv_budget(lib, ncv, 1 / 3), max_batch=8, streams=2,
+                     deposit_every=4, height0=1.0, height_decay=10000.0)
     _register(srv, wk)
+    from paper_1609_09833_amd.examples import serve_driver
+    eng = serve_driver.Engines(srv, wk)
+    srv.start()
     t, w, step = W.serving_requests(seed=4, n_walkers=wk.nw, rate=50_000.0, n_requests=240)
-    out = srv.replay(w, step, t)
-    assert out["stats"]["completed"] == len(t) and out["stats"]["evictions"] > 0
+    out = serve_driver.replay(srv, eng, w, step, t, AMP)
+    srv.stop()
+    st = srv.stats()
+    assert st["completed"] == len(t) and st["evictions"] > 0
     centers, heights = lib.abp_hills_export(ctx)
     assert np.array_equal(centers[:, :nh], cen)
     for r in range(len(t)):
-        s_o, V_o, dV_o, A0, A = _oracle_request(spec, centers, heights, wk, int(w[r]), int(step[r]),
-                                                int(out["version"][r]))
-        ds = out["s"][:, r] - s_o
-        for a in range(D):
-            if periodic[a]:
-                ds[a] = _wrap(ds[a])
-        assert np.abs(ds).max() < 1e-12, (r, ds)
-        check_bound("served V", np.array([out["V"][r]]), np.array([V_o]), np.array([A0]))
-        check_bound("served dVds", out["dVds"][:, r], dV_o, A)
+        o, k3 = int(out["offset"][r]), 3 * int(eng.n_cv[w[r]])
+        _check_request(f"{D}-D served", spec, centers, heights, wk, srv, r, int(w[r]), out["positions"][o:o + k3],
+                       int(out["version"][r]), out["s"][:, r], out["V"][r], out["dVds"][:, r],
+                       out["forces"][o:o + k3])
     srv.close()
     ctx.close()
