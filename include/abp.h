@@ -294,11 +294,14 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  *
  * A walker's CV atoms are the distinct atoms of its CV lists, in increasing
  * index order (abp_server_walker_atoms); positions are submitted and forces
- * returned in that order. While a walker is resident its device state is
- * ABP_SERVER_BYTES_PER_ATOM bytes per CV atom (positions, masses, forces);
- * walkers are admitted first come first served against the HBM budget, and
- * the least recently used idle walker is evicted when memory is short
- * (admission copies its CV-atom masses to the device once). A walker has at
+ * returned in that order. Positions and forces travel zero-copy: the kernels
+ * read a request's positions from pinned, mapped host staging and write its
+ * forces there. While a walker is resident its device state is its CV-atom
+ * masses (ABP_SERVER_BYTES_PER_ATOM bytes per CV atom; its CV lists are copied
+ * to the device once, at start); walkers are admitted first come first served
+ * against the HBM budget, and the least recently used idle walker is evicted
+ * when memory is short (admission sends its masses with its next batch). A
+ * walker has at
  * most one request in the device at a time, and its requests run in
  * submission order. A batch is formed from the resident walkers with a
  * request whenever one of `streams` batch slots is free; up to `streams`
@@ -311,10 +314,11 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  * runs in. Forces are FP32; s, V and dV/ds FP64. */
 typedef struct abp_server abp_server;
 
-#define ABP_SERVER_BYTES_PER_ATOM 28  /* seven FP32 device arrays per CV atom: x, y, z, mass, fx, fy, fz */
+#define ABP_SERVER_BYTES_PER_ATOM 4   /* resident device state per CV atom: its FP32 mass */
 
 typedef struct {
-  int64_t hbm_budget_bytes;  /* device memory for resident walker state (ABP_SERVER_BYTES_PER_ATOM per CV atom) */
+  int64_t hbm_budget_bytes;  /* device memory for resident walker state (ABP_SERVER_BYTES_PER_ATOM per CV atom)
+                                beyond the registered CV lists */
   int32_t max_batch;         /* requests per batch, 1..65536 (1 = one launch per request) */
   int32_t streams;           /* batches in flight, 1..8 */
   int32_t deposit_every;     /* deposit period in steps; 0: never */

@@ -23,7 +23,7 @@ ABP_K_GAUSS, ABP_K_COMPACT = 0, 1
 ABP_T_PLAIN, ABP_T_MABP = 0, 1
 ABP_EVAL_DIRECT, ABP_EVAL_GRID = 0, 1
 ABP_CV_COM_DIST, ABP_CV_TORSION, ABP_CV_RMSD_OFF = 0, 1, 2
-ABP_SERVER_BYTES_PER_ATOM = 28          # device pool bytes per CV atom of a resident walker
+ABP_SERVER_BYTES_PER_ATOM = 4           # resident device bytes per CV atom (its mass)
 
 EXPORTED = ("abp_create", "abp_destroy", "bias_deposit", "bias_eval", "cv_compute", "bias_force",
             "abp_set_force_shape", "abp_reserve", "abp_commit", "abp_sync", "abp_num_hills", "abp_hills_export",

@@ -121,6 +121,15 @@ struct ForceArgs {
   float* fx;
   float* fy;
   float* fz;
+  // Masses at mass[mass_base[w] + i] instead of mass[atom_base[w] + i] (NULL:
+  // atom_base). A walker with stage_off[w] >= 0 reads its masses from
+  // stage_mass[stage_off[w] + i] and stores them to mass_store[mass_base[w] + i]
+  // (a walker admitted to the serving loop's device pool for this batch).
+  const int64_t* mass_base;
+  const int64_t* stage_off;
+  const float* stage_mass;
+  float* mass_store;
+  int32_t force_store;             // 1: forces start at zero; the one-pass chain rule writes, not adds
   const int64_t* n_visible;        // [nw] or NULL
   int64_t n_visible_default;       // used when n_visible is NULL
   const int64_t* deposit_slot;     // [nw] or NULL

@@ -228,8 +228,10 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
 
 // Chain rule for one walker (all threads of the block; S.dV set).
 template <int D>
-__device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const Entry (&ent)[kCache]) {
+__device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const Entry (&ent)[kCache]) {
   const int tid = threadIdx.x;
+  const int64_t base = A.atom_base[w];
+  const int64_t mbase = A.mass_base ? A.mass_base[w] : base;
   if (S.fast) {
     // Every cached COM/RMSD entry is a distinct atom here (no atom is in two
     // such lists and each list is strictly increasing), so all the old forces
@@ -285,7 +287,7 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
 #pragma unroll
     for (int k = 0; k < kCache; ++k) {
       old[k][0] = old[k][1] = old[k][2] = 0.0f;
-      if (!live[k]) continue;
+      if (!live[k] || A.force_store) continue;
       old[k][0] = A.fx[gat[k]];
       old[k][1] = A.fy[gat[k]];
       old[k][2] = A.fz[gat[k]];
@@ -339,8 +341,9 @@ __device__ void apply_forces(const ForceArgs& A, int64_t base, CvState& S, const
         const double scale = t == 0 ? -g * S.cv[a][3] : g * S.cv[a][4];
         const int b0 = S.lb[2 * a + t], n = S.ln[2 * a + t];
         for (int e = b0 + tid; e < b0 + n; e += kFBlock) {
-          const int64_t gi = base + A.list_idx[e];
-          const double c = scale * (double)A.mass[gi];
+          const int32_t li = A.list_idx[e];
+          const int64_t gi = base + li;
+          const double c = scale * (double)A.mass[mbase + li];
           rmw_force(A.fx, gi, c * ux);
           rmw_force(A.fy, gi, c * uy);
           rmw_force(A.fz, gi, c * uz);
@@ -382,6 +385,8 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   const ForceArgs& A = F.A;
   const int tid = threadIdx.x;
   const int64_t base = A.atom_base[w];
+  const int64_t mbase = A.mass_base ? A.mass_base[w] : base;
+  const int64_t soff = A.stage_off ? A.stage_off[w] : -1;       // masses staged for this batch
   const int32_t natoms = A.n_atoms[w];
   if (tid == 0) {
     int bad = natoms < 0 ? kErrInval : 0;
@@ -462,8 +467,10 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
     G.x = 0.0f; G.y = 0.0f; G.z = 0.0f; G.m = 0.0f; G.rx = 0.0f; G.ry = 0.0f; G.rz = 0.0f;
     const bool ok = G.li >= 0 && G.i >= 0 && G.i < natoms;
     if (natoms >= 1) {                                   // uniform
-      const int64_t g = base + (ok ? G.i : 0);
-      G.x = A.x[g]; G.y = A.y[g]; G.z = A.z[g]; G.m = A.mass[g];
+      const int32_t i = ok ? G.i : 0;
+      const int64_t g = base + i;
+      G.x = A.x[g]; G.y = A.y[g]; G.z = A.z[g];
+      G.m = soff >= 0 ? A.stage_mass[soff + i] : A.mass[mbase + i];
     }
     if (any_ref) {                                       // uniform; RMSD lists are not empty
       const int e = G.li >= 0 ? G.e : 0;
@@ -504,6 +511,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
       S.tatom[a][jt] = i;
     }
     if (r < kMaxCached) sh_list[r] = i;
+    if (soff >= 0) A.mass_store[mbase + i] = m;         // the walker's masses stay on the device
     out.gi = i; out.li = li; out.e = e; out.m = m;
   };
   {
@@ -754,7 +762,7 @@ __device__ void finish_common(const FArgs& F, int64_t w, const float (&hi)[D + 1
     write_outputs<D>(F, w, S, V);
   }
   __syncthreads();
-  apply_forces<D>(F.A, F.A.atom_base[w], S, ent);
+  apply_forces<D>(F.A, w, S, ent);
 }
 
 // ---------------------------------------------------------------------------
@@ -802,7 +810,7 @@ __global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
       write_outputs<D>(F, w, S, V);
     }
     __syncthreads();
-    apply_forces<D>(A, A.atom_base[w], S, ent);
+    apply_forces<D>(A, w, S, ent);
   }
 }
 

@@ -16,12 +16,16 @@
 //   3. admits waiting walkers first come first served into the device pool,
 //      evicting least recently used idle walkers when the budget is short,
 //   4. if a batch slot is free, forms a batch from the walkers that are
-//      resident, idle and have a request, and enqueues on the slot's stream:
+//      resident, idle and have a request, and enqueues on the slot's stream
 //      the descriptor upload (with the masses of walkers admitted for it),
-//      the stage launch (positions from the requests' mapped host staging into
-//      the pool, forces cleared), the bias-force launches (they write s, V,
-//      dV/ds straight into mapped host memory), the gather launch (forces back
-//      to the requests' staging) and an event.
+//      the bias-force launches and an event.
+// Positions and forces never pass through device copies: the bias-force
+// kernels read each request's CV-atom positions from its pinned, mapped
+// host staging and write the forces there (posted writes, no read-back), and
+// write s, V and dV/ds straight into mapped host memory. A walker's resident
+// device state is its CV-atom masses (the pool the budget bounds); a walker
+// admitted for a batch gets its masses in the batch descriptor, and the CV
+// stage stores them into its pool range for later batches.
 // Requests in one batch see the same history version (hills committed when
 // the batch was formed); deposits go to slots reserved in formation order.
 // Every buffer is sized at start: the loop itself allocates nothing.
@@ -58,7 +62,6 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
 
 constexpr int kMaxLists = 6;
 constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;
-constexpr int kPoolArrays = 7;                 // x, y, z, mass, fx, fy, fz
 constexpr size_t kTraceMax = (size_t)1 << 20;  // batch records kept
 constexpr double kSpinSeconds = 2e-3;          // idle time the scheduler spins before it sleeps
 
@@ -83,7 +86,7 @@ struct Record {              // one request from submit to poll
   int32_t walker = -1;
   int32_t n_cv = 0;
   int64_t step = 0;
-  int64_t arena_off = 0;     // floats: x, y, z, fx, fy, fz blocks of n_cv each
+  int64_t arena_off = 0;     // first float of its strip: x, y, z, fx, fy, fz blocks of max_cv each
   float* force_out = nullptr;
   double t_submit = 0.0, t_done = 0.0;
   int64_t version = 0, dep_slot = -1;
@@ -151,7 +154,7 @@ struct abp_server {
   float* d_ry = nullptr;
   float* d_rz = nullptr;
   int64_t pool_atoms = 0;
-  float* d_pool = nullptr;           // kPoolArrays arrays of pool_atoms floats
+  float* d_pool = nullptr;           // CV-atom masses of resident walkers, pool_atoms floats
   abp::RangePool free_atoms;         // free pool ranges, best fit
   std::list<int32_t> lru;            // idle resident walkers, least recent first
   std::deque<int32_t> admission;     // walkers waiting for memory
@@ -161,11 +164,13 @@ struct abp_server {
   hipStream_t commit_stream = nullptr;
   std::map<int64_t, bool> dep_done;  // reserved slot -> done
   int64_t resident = 0;
-  // request staging: max_pending records, each with a fixed range of the
-  // pinned, mapped arena (6 * max_cv floats)
+  // request staging: max_pending records, each with a fixed strip of the
+  // pinned, mapped arena: x, y, z, fx, fy, fz blocks of `block` floats
+  // (block = the largest walker's CV atoms), so that block offsets are the
+  // same for every request and one base per request addresses all six
   float* arena = nullptr;
   float* d_arena = nullptr;
-  int64_t stride = 0;
+  int64_t block = 0;
   std::vector<Record> records;
   // shared between the callers and the scheduler
   std::mutex mu_in;                  // incoming, free_records, next_id
@@ -195,8 +200,6 @@ namespace {
 double now_s(const abp_server* S) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
 }
-
-float* pool_array(abp_server* S, int which) { return S->d_pool + (int64_t)which * S->pool_atoms; }
 
 // Returns every resident walker to the pool and clears all queues.
 void reset_residency(abp_server* S) {
@@ -291,7 +294,7 @@ abp_status commit_prefix(abp_server* S) {
 abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int32_t* recs, int64_t nb,
                          int32_t shape, bool deposits) {
   DescLayout L(nb, S->nlists);
-  int64_t* d_pool = reinterpret_cast<int64_t*>(sl.h_desc + L.pool_off);
+  int64_t* d_poolo = reinterpret_cast<int64_t*>(sl.h_desc + L.pool_off);
   int64_t* d_arena = reinterpret_cast<int64_t*>(sl.h_desc + L.arena_off);
   int64_t* d_stage = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
   int64_t* d_dep = reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
@@ -310,7 +313,7 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
     Walker& w = S->walkers[wids[j]];
     const Record& R = S->records[recs[j]];
     sl.reqs.push_back(recs[j]);
-    d_pool[j] = w.pool_off;
+    d_poolo[j] = w.pool_off;
     d_arena[j] = R.arena_off;
     d_ncv[j] = w.n_cv;
     d_stage[j] = -1;
@@ -347,22 +350,7 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
   sl.nb = nb;
   SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float), hipMemcpyHostToDevice,
                          sl.stream));
-  abp::ServeArgs E;
-  E.nb = nb;
-  E.pool_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.pool_off);
-  E.arena_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.arena_off);
-  E.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
-  E.n_cv = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_cv);
-  E.stage_mass = reinterpret_cast<const float*>(sl.d_desc + L.total);
-  E.arena = S->d_arena;
-  E.x = pool_array(S, 0);
-  E.y = pool_array(S, 1);
-  E.z = pool_array(S, 2);
-  E.mass = pool_array(S, 3);
-  E.fx = pool_array(S, 4);
-  E.fy = pool_array(S, 5);
-  E.fz = pool_array(S, 6);
-  SRV_TRY(abp::launch_serve_stage(E, sl.stream));
+  const int64_t M = S->block;
   abp::ForceArgs A;
   std::memset(&A, 0, sizeof(A));
   A.ncv = S->ncv;
@@ -374,15 +362,20 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
   A.ref_y = S->d_ry;
   A.ref_z = S->d_rz;
   A.nw = nb;
-  A.atom_base = E.pool_off;
-  A.n_atoms = E.n_cv;
-  A.x = E.x;
-  A.y = E.y;
-  A.z = E.z;
-  A.mass = E.mass;
-  A.fx = E.fx;
-  A.fy = E.fy;
-  A.fz = E.fz;
+  A.atom_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.arena_off);   // each request's strip
+  A.n_atoms = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_cv);
+  A.x = S->d_arena;
+  A.y = S->d_arena + M;
+  A.z = S->d_arena + 2 * M;
+  A.fx = S->d_arena + 3 * M;
+  A.fy = S->d_arena + 4 * M;
+  A.fz = S->d_arena + 5 * M;
+  A.mass = S->d_pool;
+  A.mass_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.pool_off);
+  A.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
+  A.stage_mass = reinterpret_cast<const float*>(sl.d_desc + L.total);
+  A.mass_store = S->d_pool;
+  A.force_store = 1;                      // the strips' forces were zeroed at submit
   A.n_visible = nullptr;
   A.n_visible_default = sl.version;
   A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(sl.d_desc + L.dep_slot) : nullptr;
@@ -394,7 +387,6 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
   A.shape = shape;
   A.err = S->cv.err;
   SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
-  SRV_TRY(abp::launch_serve_gather(E, sl.stream));
   SRV_TRY(hipEventRecord(sl.done, sl.stream));
   sl.busy = true;
   return ABP_OK;
@@ -581,21 +573,21 @@ abp_status size_buffers(abp_server* S) {
       return sfail(ABP_E_NOMEM, "cannot allocate batch descriptors");
     sl.desc_cap = need;
   }
-  const int64_t stride = 6 * (int64_t)std::max(S->max_cv, 1);
-  if (stride != S->stride || !S->arena) {
+  const int64_t block = std::max(S->max_cv, 1);
+  if (block != S->block || !S->arena) {
     if (S->arena) SRV_TRY(hipHostFree(S->arena));
     S->arena = nullptr;
     S->d_arena = nullptr;
-    const size_t bytes = sizeof(float) * (size_t)stride * (size_t)S->desc.max_pending;
+    const size_t bytes = sizeof(float) * 6 * (size_t)block * (size_t)S->desc.max_pending;
     if (hipHostMalloc((void**)&S->arena, bytes, hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer((void**)&S->d_arena, S->arena, 0) != hipSuccess)
       return sfail(ABP_E_NOMEM, "cannot allocate the request staging");
-    S->stride = stride;
+    S->block = block;
   }
   S->records.assign(S->desc.max_pending, Record());
   S->free_records.clear();
   for (int32_t r = S->desc.max_pending - 1; r >= 0; --r) {
-    S->records[r].arena_off = (int64_t)r * stride;
+    S->records[r].arena_off = (int64_t)r * 6 * block;
     S->free_records.push_back(r);
   }
   const abp_status st = abp::ctx_reserve_commit(S->ctx, (int64_t)S->desc.max_batch * S->desc.streams);
@@ -620,7 +612,7 @@ abp_status warm_up(abp_server* S) {
   R.walker = 0;
   R.n_cv = w.n_cv;
   R.step = 0;
-  std::memset(S->arena + R.arena_off, 0, sizeof(float) * 6 * (size_t)w.n_cv);
+  std::memset(S->arena + R.arena_off, 0, sizeof(float) * 6 * (size_t)S->block);
   const int32_t wid = 0;
   Slot& sl = S->slots[0];
   const int nshapes = abp_num_hills(S->ctx) > 0 ? 3 : 1;
@@ -684,7 +676,7 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     return sfail(ABP_E_DEVICE, "cannot select the context's device");
   }
   S->pool_atoms = desc->hbm_budget_bytes / kBytesPerAtom;
-  if (hipMalloc(&S->d_pool, sizeof(float) * kPoolArrays * S->pool_atoms) != hipSuccess) {
+  if (hipMalloc(&S->d_pool, sizeof(float) * S->pool_atoms) != hipSuccess) {
     delete S;
     return sfail(ABP_E_NOMEM, "cannot allocate the walker pool");
   }
@@ -921,7 +913,12 @@ abp_status abp_server_submit(abp_server* S, int32_t walker, int64_t step, const 
     id = S->next_id++;
   }
   Record& R = S->records[r];
-  std::memcpy(S->arena + R.arena_off, xyz, sizeof(float) * 3 * (size_t)n);
+  float* strip = S->arena + R.arena_off;
+  const int64_t M = S->block;
+  for (int c = 0; c < 3; ++c) {
+    std::memcpy(strip + c * M, xyz + (int64_t)c * n, sizeof(float) * (size_t)n);
+    std::memset(strip + (3 + c) * M, 0, sizeof(float) * (size_t)n);     // forces accumulate from zero
+  }
   R.id = id;
   R.walker = walker;
   R.n_cv = n;
@@ -974,7 +971,9 @@ abp_status abp_server_poll(abp_server* S, abp_server_result* out, int64_t max, i
     }
     o.V = R.V;
     if (R.force_out)
-      std::memcpy(R.force_out, S->arena + R.arena_off + 3 * (int64_t)R.n_cv, sizeof(float) * 3 * (size_t)R.n_cv);
+      for (int c = 0; c < 3; ++c)
+        std::memcpy(R.force_out + (int64_t)c * R.n_cv, S->arena + R.arena_off + (3 + c) * S->block,
+                    sizeof(float) * (size_t)R.n_cv);
   }
   if (!take.empty()) {
     std::lock_guard<std::mutex> lk(S->mu_in);
