@@ -237,6 +237,23 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
                       const int64_t* deposit_slot, const double* deposit_height,
                       double* s, double* V, double* dVds, abp_stream stream);
 
+/* bias_force for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, kernels and results as bias_force, but the workspace of the split
+ * and chained launch shapes is a fixed 64 MiB device array of the library
+ * (one per GPU, held from the first abp_create on that GPU until the process
+ * ends) instead of the context's grow-on-demand buffer, so the call never
+ * allocates. ABP_E_NOMEM (nothing enqueued) when the launch needs more
+ * workspace than that: it needs about nw * (13 KB + 8 (ncv + 1) B per 64
+ * committed hills) for histories longer than 16,384 hills (e.g. 1,024
+ * walkers up to about 140,000 hills in 2-D); fused and grid launches need
+ * none. Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams, other contexts, other host threads) race. */
+abp_status bias_force_noalloc(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
+                              const abp_walkers* walkers, const int64_t* n_visible,
+                              const int64_t* deposit_slot, const double* deposit_height,
+                              double* s, double* V, double* dVds, abp_stream stream);
+
 /* Launch shapes of bias_force's direct sum (see bias_force). */
 typedef enum {
   ABP_SHAPE_AUTO = 0,    /* fused up to 16,384 hills; then chained for 1-2 walkers, else split */

@@ -26,6 +26,7 @@ ABP_CV_COM_DIST, ABP_CV_TORSION, ABP_CV_RMSD_OFF = 0, 1, 2
 ABP_SERVER_BYTES_PER_ATOM = 4           # resident device bytes per CV atom (its mass)
 
 EXPORTED = ("abp_create", "abp_destroy", "bias_deposit", "bias_eval", "cv_compute", "bias_force",
+            "bias_force_noalloc",
             "abp_set_force_shape", "abp_reserve", "abp_commit", "abp_sync", "abp_num_hills", "abp_hills_export",
             "abp_grid_export", "abp_status_str", "abp_last_error",
             "abp_server_create", "abp_server_destroy", "abp_server_add_walker", "abp_server_walker_atoms",
@@ -99,6 +100,7 @@ def _load():
         "bias_eval": ([P, i32, i32, i64, i32, P, i64, P, P, P], i32),
         "cv_compute": ([P, P, P, P, P], i32),
         "bias_force": ([P, i32, i32, P, P, P, P, P, P, P, P, P], i32),
+        "bias_force_noalloc": ([P, i32, i32, P, P, P, P, P, P, P, P, P], i32),
         "abp_reserve": ([P, i64, P], i32),
         "abp_commit": ([P, i64, P], i32),
         "abp_sync": ([P, P], i32),
@@ -299,6 +301,19 @@ def bias_force(ctx, walkers, mode=ABP_EVAL_DIRECT, prec=ABP_PREC_FP32_KAHAN, n_v
                deposit_slot=None, deposit_height=None, s=None, V=None, dVds=None, stream=None):
     """Fused CV -> bias -> chain-rule step; forces are added into walkers.fx/fy/fz.
     Returns (s[ncv][nw], V[nw], dVds[ncv][nw]) as float64 device tensors."""
+    return _bias_force(lib.bias_force, ctx, walkers, mode, prec, n_visible, deposit_slot, deposit_height, s, V,
+                       dVds, stream)
+
+
+def bias_force_noalloc(ctx, walkers, mode=ABP_EVAL_DIRECT, prec=ABP_PREC_FP32_KAHAN, n_visible=None,
+                       deposit_slot=None, deposit_height=None, s=None, V=None, dVds=None, stream=None):
+    """bias_force whose workspace is the library's fixed device array (the C
+    call allocates nothing; pass preallocated s, V, dVds to allocate nothing here)."""
+    return _bias_force(lib.bias_force_noalloc, ctx, walkers, mode, prec, n_visible, deposit_slot, deposit_height,
+                       s, V, dVds, stream)
+
+
+def _bias_force(fn, ctx, walkers, mode, prec, n_visible, deposit_slot, deposit_height, s, V, dVds, stream):
     nw, ncv, dev = walkers.nw, walkers.ncv, ctx.device
     if s is None:
         s = torch.full((ncv, nw), float("nan"), dtype=torch.float64, device=dev)
@@ -310,8 +325,8 @@ def bias_force(ctx, walkers, mode=ABP_EVAL_DIRECT, prec=ABP_PREC_FP32_KAHAN, n_v
     slot = None if deposit_slot is None else _dev(deposit_slot, dev, torch.int64)
     hgt = None if deposit_height is None else _dev(deposit_height, dev, torch.float64)
     cv, wk = walkers.cv_desc(), walkers.walkers_desc()
-    _check(lib.bias_force(ctx.handle, int(mode), int(prec), C.byref(cv), C.byref(wk), _ptr(nvis), _ptr(slot),
-                          _ptr(hgt), _ptr(s), _ptr(V), _ptr(dVds), _stream(stream)))
+    _check(fn(ctx.handle, int(mode), int(prec), C.byref(cv), C.byref(wk), _ptr(nvis), _ptr(slot),
+              _ptr(hgt), _ptr(s), _ptr(V), _ptr(dVds), _stream(stream)))
     return s, V, dVds
 
 

@@ -323,6 +323,12 @@ abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out) {
     delete ctx;
     return fail(ABP_E_NOMEM, "device allocation failed (capacity %lld)", (long long)cap);
   }
+  st = abp::noalloc_setup(device);      // bias_force_noalloc's static workspace on this device
+  if (st != ABP_OK) {
+    free_all(ctx);
+    delete ctx;
+    return st;
+  }
   *out = ctx;
   return ok();
 }
@@ -424,34 +430,17 @@ abp_status bias_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp
                       const abp_walkers* walkers, const int64_t* n_visible,
                       const int64_t* deposit_slot, const double* deposit_height,
                       double* s, double* V, double* dVds, abp_stream stream) {
-  if (!ctx) return fail(ABP_E_INVAL, "context is NULL");
-  abp_status st = check_cv(ctx, cv, walkers);
-  if (st != ABP_OK) return st;
-  if (prec != ABP_PREC_FP32_KAHAN && prec != ABP_PREC_FP32_NAIVE && prec != ABP_PREC_FP64)
-    return fail(ABP_E_INVAL, "unknown precision mode");
-  if (mode != ABP_EVAL_DIRECT && mode != ABP_EVAL_GRID) return fail(ABP_E_INVAL, "unknown eval mode");
-  if (mode == ABP_EVAL_GRID && !ctx->grid) return fail(ABP_E_INVAL, "context has no grid");
-  if (walkers->nw == 0) return ok();
-  if (!s || !V || !dVds) return fail(ABP_E_INVAL, "s, V or dVds is NULL");
-  if (!walkers->fx || !walkers->fy || !walkers->fz) return fail(ABP_E_INVAL, "force arrays are NULL");
+  abp::ForceCall call;
+  abp_status st = abp::prepare_force(ctx, mode, prec, cv, walkers, n_visible, deposit_slot, deposit_height, s, V,
+                                     dVds, &call);
+  if (st != ABP_OK || call.nothing) return st;
   DeviceGuard guard(ctx->device);
-  abp::ForceArgs A = force_args(ctx, cv, walkers);
-  A.n_visible = n_visible;
-  A.deposit_slot = deposit_slot;
-  A.deposit_height = deposit_height;
-  A.s = s;
-  A.V = V;
-  A.dVds = dVds;
-  A.use_grid = mode == ABP_EVAL_GRID ? 1 : 0;
-  A.grid = ctx->grid;
-  A.prec = prec;
-  A.shape = ctx->force_shape;
-  if (abp::force_uses_workspace(walkers->nw, ctx->committed, A.use_grid, 0, A.shape)) {
+  if (call.workspace_bytes) {
     const int nbw = abp::force_blocks_per_walker(ctx->committed, 0, 0);
     st = force_workspace(ctx, walkers->nw, nbw);
     if (st != ABP_OK) return st;
   }
-  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), A, ctx->fws, (hipStream_t)stream));
+  HIP_TRY(abp::launch_bias_force(ctx->K, ctx->hist(), call.A, ctx->fws, (hipStream_t)stream));
   return ok();
 }
 
@@ -560,6 +549,43 @@ CtxView ctx_view(abp_ctx* ctx) {
 }
 
 int64_t ctx_reserved(const abp_ctx* ctx) { return ctx->reserved; }
+
+abp_status prepare_force(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, const abp_cv_desc* cv,
+                         const abp_walkers* walkers, const int64_t* n_visible, const int64_t* deposit_slot,
+                         const double* deposit_height, double* s, double* V, double* dVds, ForceCall* out) {
+  out->nothing = true;
+  out->workspace_bytes = 0;
+  if (!ctx) return fail(ABP_E_INVAL, "context is NULL");
+  abp_status st = check_cv(ctx, cv, walkers);
+  if (st != ABP_OK) return st;
+  if (prec != ABP_PREC_FP32_KAHAN && prec != ABP_PREC_FP32_NAIVE && prec != ABP_PREC_FP64)
+    return fail(ABP_E_INVAL, "unknown precision mode");
+  if (mode != ABP_EVAL_DIRECT && mode != ABP_EVAL_GRID) return fail(ABP_E_INVAL, "unknown eval mode");
+  if (mode == ABP_EVAL_GRID && !ctx->grid) return fail(ABP_E_INVAL, "context has no grid");
+  if (walkers->nw == 0) return ok();
+  if (!s || !V || !dVds) return fail(ABP_E_INVAL, "s, V or dVds is NULL");
+  if (!walkers->fx || !walkers->fy || !walkers->fz) return fail(ABP_E_INVAL, "force arrays are NULL");
+  ForceArgs A = force_args(ctx, cv, walkers);
+  A.n_visible = n_visible;
+  A.deposit_slot = deposit_slot;
+  A.deposit_height = deposit_height;
+  A.s = s;
+  A.V = V;
+  A.dVds = dVds;
+  A.use_grid = mode == ABP_EVAL_GRID ? 1 : 0;
+  A.grid = ctx->grid;
+  A.prec = prec;
+  A.shape = ctx->force_shape;
+  out->A = A;
+  out->device = ctx->device;
+  out->K = ctx->K;
+  out->H = ctx->hist();
+  if (force_uses_workspace(walkers->nw, ctx->committed, A.use_grid, 0, A.shape))
+    out->workspace_bytes = force_workspace_bytes(walkers->nw, force_blocks_per_walker(ctx->committed, 0, 0),
+                                                 ctx->desc.ndim);
+  out->nothing = false;
+  return ok();
+}
 
 abp_status ctx_reserve_commit(abp_ctx* ctx, int64_t n) {
   if (!ctx->grid || n <= 0) return ok();
