@@ -362,13 +362,16 @@ def grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV):
                                     "note": "FP64 MFMA deposit; the timed call includes the history append "
                                             "and the split reduction"}
 
-    def grid_step():
-        abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, V=V, dVds=dV)
-    el3, _ = timed(grid_step, args.steps, 2, stream)
-    extra["grid_eval"] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
-                          "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9,
-                          "frac_hbm_compulsory": nq * 20 * args.steps / el3 / 1e9 / HBM_PEAK_GBS}
-    log(f"bench: grid eval {nq * args.steps / el3:.4e} walker-steps/s, build {extra['grid_build_ms']:.2f} ms")
+    for key, prec in (("grid_eval", abp.ABP_PREC_FP64), ("grid_eval_fp32_nodes", abp.ABP_PREC_FP32_KAHAN)):
+        def grid_step(prec=prec):
+            abp.bias_eval(gctx, qd, mode=abp.ABP_EVAL_GRID, prec=prec, V=V, dVds=dV)
+        el3, _ = timed(grid_step, args.steps, 2, stream)
+        extra[key] = {"walker_steps_per_s": nq * args.steps / el3, "ms_per_step": el3 / args.steps * 1e3,
+                      "node_values": "FP64" if prec == abp.ABP_PREC_FP64 else "FP32 mirror",
+                      "hbm_GBs_compulsory": nq * 20 * args.steps / el3 / 1e9,
+                      "frac_hbm_compulsory": nq * 20 * args.steps / el3 / 1e9 / HBM_PEAK_GBS}
+        log(f"bench: {key} {nq * args.steps / el3:.4e} walker-steps/s ({el3 / args.steps * 1e6:.1f} us)")
+    log(f"bench: grid build {extra['grid_build_ms']:.2f} ms")
     gctx.close()
     return extra
 

@@ -194,7 +194,11 @@ abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* ce
  * tensor-product cubic Hermite polynomials from the value and derivative
  * arrays, clamping non-periodic coordinates to [lo, hi].
  * Outputs V[nq] and dVds[ndim][nq] have the same dtype as q.
- * prec selects the hill-sum arithmetic; the grid path always uses FP64.
+ * prec selects the hill-sum arithmetic. GRID: ABP_PREC_FP64 interpolates the
+ * FP64 node arrays in FP64; the FP32 modes interpolate their FP32 mirror
+ * (refreshed after every grid update; half the gathered bytes) in FP32 after
+ * locating the cell in FP64 (errors of 2^-24 of the values, and of 2^-24 |V|
+ * over the node spacing in the gradient).
  * The result for a query depends only on that query and the hills, not on nq
  * or its position in the batch. A query with a non-finite coordinate gets NaN
  * in V and all of its dVds entries (every mode and precision; it is not an

@@ -230,9 +230,12 @@ def bias_deposit(ctx, centers, heights, stream=None):
     _check(lib.bias_deposit(ctx.handle, n, _dtype_code(centers), _ptr(centers), _ptr(heights), _stream(stream)))
 
 
-def bias_eval(ctx, q, mode=ABP_EVAL_DIRECT, prec=ABP_PREC_FP32_KAHAN, n_visible=-1, V=None, dVds=None,
-              stream=None):
-    """V[nq], dVds[ndim][nq] at queries q[ndim][nq] (device tensor, float32 or float64)."""
+def bias_eval(ctx, q, mode=ABP_EVAL_DIRECT, prec=None, n_visible=-1, V=None, dVds=None, stream=None):
+    """V[nq], dVds[ndim][nq] at queries q[ndim][nq] (device tensor, float32 or float64).
+    prec None: FP32 + Kahan for DIRECT, the FP64 node arrays for GRID (an FP32
+    precision reads the grid's FP32 mirror)."""
+    if prec is None:
+        prec = ABP_PREC_FP64 if mode == ABP_EVAL_GRID else ABP_PREC_FP32_KAHAN
     q = _dev(q, ctx.device)
     nq = int(q.shape[1])
     if q.shape[0] != ctx.ndim:

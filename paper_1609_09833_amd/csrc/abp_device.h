@@ -220,8 +220,8 @@ __device__ __forceinline__ void apply_transform(const Consts& K, double h, const
 }
 
 // ---------------------------------------------------------------------------
-// Tensor-product cubic Hermite interpolation of the node arrays
-// grid[node][2^D] (value, first and mixed derivatives) at one point.
+// Tensor-product cubic Hermite interpolation of the FP64 node arrays
+// grid[node][2^D] (value, first and mixed derivatives) at one point, in FP64.
 // Returns h and the analytic gradient; *clamped is set when a non-periodic
 // coordinate lay outside [lo, hi].
 // ---------------------------------------------------------------------------
@@ -328,6 +328,214 @@ __device__ __forceinline__ void hermite_eval(const Consts& K, const double* __re
   h = val;
 #pragma unroll
   for (int k = 0; k < D; ++k) dh[k] = g[k];
+}
+
+// ---------------------------------------------------------------------------
+// The FP32 mirror of the node arrays. 1-D and 2-D grids: cell-major, cell
+// (j0, j1) = the cell whose lower corner is node (j0, j1), cell index
+// j0 + n0 j1, holding its 2^D corners (corner bit i: upper end on axis i,
+// wrapped on periodic axes) x 2^D entries: 16 or 64 bytes, one cache line per
+// query. 3-D grids (a cell record would be 256 bytes): node-major like the
+// FP64 arrays. Cells past a non-periodic axis's last node are unused.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool mirror_cells(const Consts& K) { return K.ndim <= 2; }
+
+// Offset in the mirror of entry m of node (j[0], j[1], j[2]).
+__device__ __forceinline__ int64_t mirror_node_entry(const Consts& K, const int64_t* j, int m) {
+  const int NM = 1 << K.ndim;
+  if (!mirror_cells(K)) {
+    int64_t node = 0, stride = 1;
+    for (int i = 0; i < K.ndim; ++i) {
+      node += j[i] * stride;
+      stride *= K.grid_n[i];
+    }
+    return node * NM + m;
+  }
+  // the node is corner 0 of its own cell, or, at the last node of a
+  // non-periodic axis, the upper corner of the cell below
+  int64_t cell = 0, stride = 1;
+  int corner = 0;
+  for (int i = 0; i < K.ndim; ++i) {
+    int64_t ji = j[i];
+    if (!K.periodic[i] && ji == K.grid_n[i] - 1 && ji > 0) {
+      ji -= 1;
+      corner |= 1 << i;
+    }
+    cell += ji * stride;
+    stride *= K.grid_n[i];
+  }
+  return (cell * NM + corner) * NM + m;
+}
+
+// ---------------------------------------------------------------------------
+// The interpolation from the FP32 mirror, in FP32 arithmetic: the cell and
+// the fraction t are located in FP64 (so t carries the query's own
+// precision), the basis polynomials and the sums run in FP32. Its rounding is
+// of the order of the node values' own FP32 rounding (2^-24 relative; the
+// gradient, built from differences of corner values, carries 2^-24 |h| /
+// spacing), an order below the interpolant's own error for grids fine enough
+// to resolve the hills.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void hermite_eval32(const Consts& K, const float* __restrict__ grid,
+                                               const double (&s)[D], double& h, double (&dh)[D], bool& clamped) {
+  constexpr int NM = 1 << D;
+  clamped = false;
+  if (K.quant) {
+    int64_t j[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      if (!K.periodic[i] && !(s[i] >= K.lo[i] && s[i] <= K.hi[i])) clamped = true;
+      j[i] = (int64_t)snap_index(K, i, s[i]);
+    }
+    h = (double)grid[mirror_node_entry(K, j, 0)];
+#pragma unroll
+    for (int k = 0; k < D; ++k) dh[k] = (double)grid[mirror_node_entry(K, j, 1 << k)];
+    return;
+  }
+  // per axis: the cell (lower node j0, upper j1) and the basis along it, as
+  // four weights indexed a = 2 * end + datum (datum 0: value, 1: derivative)
+  int32_t j0[D], j1[D];
+  float A[D][4], B[D][4];          // interpolant and its derivative d/ds_i
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int32_t n = K.grid_n[i];
+    const double dx = K.grid_dx[i];
+    double x = s[i], t;
+    if (K.periodic[i]) {
+      double f = (x - K.lo[i]) * K.inv_period[i];
+      f -= floor(f);
+      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
+      const double u = f * (double)n;
+      int32_t j = (int32_t)u;
+      j = j > n - 1 ? n - 1 : j;
+      t = u - (double)j;
+      j0[i] = j;
+      j1[i] = (j + 1 == n) ? 0 : j + 1;
+    } else {
+      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
+      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
+      const double u = (x - K.lo[i]) / dx;
+      int32_t j = (int32_t)u;
+      j = j > n - 2 ? n - 2 : j;
+      j = j < 0 ? 0 : j;
+      t = u - (double)j;
+      j0[i] = j;
+      j1[i] = j + 1;
+    }
+    const float tf = (float)t, dxf = (float)dx, idx = (float)(1.0 / dx);
+    const float t2 = tf * tf, t3 = t2 * tf;
+    A[i][0] = 2.0f * t3 - 3.0f * t2 + 1.0f;          // lower end, value
+    A[i][1] = (t3 - 2.0f * t2 + tf) * dxf;           // lower end, derivative
+    A[i][2] = -2.0f * t3 + 3.0f * t2;                // upper end, value
+    A[i][3] = (t3 - t2) * dxf;                       // upper end, derivative
+    B[i][0] = (6.0f * t2 - 6.0f * tf) * idx;
+    B[i][1] = 3.0f * t2 - 4.0f * tf + 1.0f;
+    B[i][2] = (-6.0f * t2 + 6.0f * tf) * idx;
+    B[i][3] = 3.0f * t2 - 2.0f * tf;
+  }
+  // the cell's data as a tensor M[a0][a1][a2] (a_i = 2 * corner bit i + entry
+  // bit i): one cell record (1-D, 2-D) or 2^D node records (3-D)
+  float Mf[NM * NM];               // flat, index sum_i a_i 4^i
+  auto put = [&](int corner, int m, float v) {
+    int at = 0, mul = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      at += (2 * ((corner >> i) & 1) + ((m >> i) & 1)) * mul;
+      mul *= 4;
+    }
+    Mf[at] = v;
+  };
+  if (D <= 2) {
+    int32_t cell = j0[0];
+    if (D == 2) cell += j0[D - 1] * K.grid_n[0];
+    const float4* src = reinterpret_cast<const float4*>(grid + (int64_t)cell * (NM * NM));
+#pragma unroll
+    for (int v = 0; v < NM * NM / 4; ++v) {
+      const float4 r = src[v];
+      const float rv[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) put((4 * v + e) / NM, (4 * v + e) % NM, rv[e]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NM; ++c) {
+      int64_t node = 0, stride = 1;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        node += (((c >> i) & 1) ? j1[i] : j0[i]) * stride;
+        stride *= K.grid_n[i];
+      }
+      const float4* src = reinterpret_cast<const float4*>(grid + node * NM);
+#pragma unroll
+      for (int v = 0; v < NM / 4; ++v) {
+        const float4 r = src[v];
+        const float rv[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) put(c, 4 * v + e, rv[e]);
+      }
+    }
+  }
+  // contract axis 0 with its value and derivative weights, then the others
+  float val = 0.0f, g[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = 0.0f;
+  if (D == 1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      val = __builtin_fmaf(A[0][a], Mf[a], val);
+      g[0] = __builtin_fmaf(B[0][a], Mf[a], g[0]);
+    }
+  } else {
+    constexpr int R = NM * NM / 4;   // entries left after contracting axis 0
+    float tA[R], tB[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float va = 0.0f, vb = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        va = __builtin_fmaf(A[0][a], Mf[4 * r + a], va);
+        vb = __builtin_fmaf(B[0][a], Mf[4 * r + a], vb);
+      }
+      tA[r] = va;
+      tB[r] = vb;
+    }
+    if (D == 2) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        val = __builtin_fmaf(A[D - 1][b], tA[b], val);
+        g[0] = __builtin_fmaf(A[D - 1][b], tB[b], g[0]);
+        g[D - 1] = __builtin_fmaf(B[D - 1][b], tA[b], g[D - 1]);
+      }
+    } else {
+      // D == 3: contract axis 1 (r = b + 4 c), then axis 2
+      float uA[4], uB0[4], uB1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          x0 = __builtin_fmaf(A[1][b], tA[(b + 4 * c) % R], x0);
+          x1 = __builtin_fmaf(A[1][b], tB[(b + 4 * c) % R], x1);
+          x2 = __builtin_fmaf(B[1][b], tA[(b + 4 * c) % R], x2);
+        }
+        uA[c] = x0;
+        uB0[c] = x1;
+        uB1[c] = x2;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k2 = D - 1;
+        val = __builtin_fmaf(A[k2][c], uA[c], val);
+        g[0] = __builtin_fmaf(A[k2][c], uB0[c], g[0]);
+        g[1 % D] = __builtin_fmaf(A[k2][c], uB1[c], g[1 % D]);
+        g[k2] = __builtin_fmaf(B[k2][c], uA[c], g[k2]);
+      }
+    }
+  }
+  h = (double)val;
+#pragma unroll
+  for (int k = 0; k < D; ++k) dh[k] = (double)g[k];
 }
 
 // ---------------------------------------------------------------------------

@@ -27,6 +27,7 @@ struct abp_ctx {
   double* l64 = nullptr;
   int4* rec32 = nullptr;
   double* grid = nullptr;
+  float* grid32 = nullptr;            // FP32 mirror of the grid, refreshed after every grid update
   int32_t* err = nullptr;
   unsigned long long* clamped = nullptr;
   double* scratch = nullptr;
@@ -263,6 +264,7 @@ abp_status grid_add(abp_ctx* ctx, int64_t k0, int64_t k1, hipStream_t stream) {
   abp_status st = grow_scratch(ctx, need);
   if (st != ABP_OK) return st;
   HIP_TRY(abp::launch_grid_deposit(ctx->K, ctx->hist(), k0, k1, ctx->grid, need ? ctx->scratch : nullptr, stream));
+  HIP_TRY(abp::launch_grid_mirror(ctx->K, ctx->grid, ctx->grid32, stream));
   return ABP_OK;
 }
 
@@ -272,6 +274,7 @@ void free_all(abp_ctx* ctx) {
   if (ctx->l64) (void)hipFree(ctx->l64);
   if (ctx->rec32) (void)hipFree(ctx->rec32);
   if (ctx->grid) (void)hipFree(ctx->grid);
+  if (ctx->grid32) (void)hipFree(ctx->grid32);
   if (ctx->err) (void)hipFree(ctx->err);
   if (ctx->clamped) (void)hipFree(ctx->clamped);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
@@ -310,11 +313,13 @@ abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out) {
               hipMalloc(&ctx->err, sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&ctx->clamped, sizeof(unsigned long long)) == hipSuccess;
   if (good && ctx->K.nodes > 0)
-    good = hipMalloc(&ctx->grid, sizeof(double) * (size_t)(ctx->K.nodes << desc->ndim)) == hipSuccess;
+    good = hipMalloc(&ctx->grid, sizeof(double) * (size_t)(ctx->K.nodes << desc->ndim)) == hipSuccess &&
+           hipMalloc(&ctx->grid32, sizeof(float) * abp::grid_mirror_floats(ctx->K)) == hipSuccess;
   if (good) {
     good = hipMemset(ctx->err, 0, sizeof(int32_t)) == hipSuccess &&
            hipMemset(ctx->clamped, 0, sizeof(unsigned long long)) == hipSuccess &&
            (!ctx->grid || hipMemset(ctx->grid, 0, sizeof(double) * (size_t)(ctx->K.nodes << desc->ndim)) == hipSuccess) &&
+           (!ctx->grid32 || hipMemset(ctx->grid32, 0, sizeof(float) * abp::grid_mirror_floats(ctx->K)) == hipSuccess) &&
            abp::launch_hist_init(ctx->hist(), desc->ndim, nullptr) == hipSuccess &&
            hipDeviceSynchronize() == hipSuccess;
   }
@@ -400,7 +405,8 @@ abp_status bias_eval(abp_ctx* ctx, abp_eval_mode mode, abp_prec prec, int64_t nq
   if (mode == ABP_EVAL_GRID) {
     if (!ctx->grid) return fail(ABP_E_INVAL, "context has no grid");
     if (n_visible != -1) return fail(ABP_E_INVAL, "GRID mode covers all committed hills (n_visible must be -1)");
-    HIP_TRY(abp::launch_grid_eval(ctx->K, ctx->grid, nq, f64, q, V, dVds, ctx->clamped, s));
+    HIP_TRY(abp::launch_grid_eval(ctx->K, ctx->grid, prec == ABP_PREC_FP64 ? nullptr : ctx->grid32, nq, f64, q, V,
+                                  dVds, ctx->clamped, s));
     return ok();
   }
   if (n_visible < -1 || n_visible > ctx->committed)

@@ -97,9 +97,15 @@ size_t grid_deposit_scratch_bytes(const Consts& K, int64_t nhills);
 hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, int64_t k1,
                                double* grid, double* scratch, hipStream_t stream);
 
-hipError_t launch_grid_eval(const Consts& K, const double* grid, int64_t nq, int q_f64,
+// grid32 (optional): the FP32 mirror of grid; when given the interpolation
+// reads it instead (FP64 arithmetic either way).
+hipError_t launch_grid_eval(const Consts& K, const double* grid, const float* grid32, int64_t nq, int q_f64,
                             const void* q, void* V, void* dVds, unsigned long long* n_clamped,
                             hipStream_t stream);
+// Refreshes the FP32 mirror grid32 of the node arrays grid (cell-major for
+// 1-D and 2-D grids, node-major for 3-D; grid_mirror_floats entries).
+size_t grid_mirror_floats(const Consts& K);
+hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, hipStream_t stream);
 
 struct ForceArgs {
   int32_t ncv;

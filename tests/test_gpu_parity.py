@@ -222,6 +222,14 @@ def test_grid_eval_matches_oracle_interpolation_and_hermite_bound(c2_grid):
     bound_v = 2 * dx ** 4 / 384 * f4 * A0
     assert np.all(np.abs(hq - hd) <= bound_v + 1e-12)
     assert np.all(np.abs(V - hd) <= bound_v + 1e-5 * (np.abs(hd) + A0))
+    # the FP32 mirror of the node arrays (FP32 modes) against the oracle's interpolation:
+    # V at 1e-6; dV at 1e-5, since value nodes rounded to FP32 (2^-24 |V|) enter the
+    # gradient divided by the node spacing (about 1.3e-6 of A here, an order below the
+    # grid's own Hermite error)
+    V32, dV32 = abp.bias_eval(ctx, to_dev(q), mode=abp.ABP_EVAL_GRID, prec=KAHAN)
+    r0 = check_bound("grid V, FP32 nodes", host(V32)[idx], hq, A0, 1e-6)
+    r1 = check_bound("grid dV, FP32 nodes", host(dV32)[:, idx], dhq, A, 1e-5)
+    print(f"C2 grid from FP32 nodes: error / bound: V {r0:.3e} (1e-6), dV {r1:.3e} (1e-5)")
 
 
 def test_grid_incremental_equals_batch():
@@ -235,6 +243,14 @@ def test_grid_incremental_equals_batch():
     np.testing.assert_allclose(H2, H1, rtol=1e-12, atol=1e-14 * np.abs(H1).max())
     Ho = oracle.grid_all(spec, hills.centers, hills.heights)
     np.testing.assert_allclose(H1, Ho, rtol=1e-9, atol=1e-12 * np.abs(Ho).max())
+    # the FP32 mirror follows every incremental deposit
+    qq = np.random.default_rng(6).uniform(-PI, PI, (2, 512))
+    hq, dhq, _ = oracle.grid_eval(spec, Ho, qq)
+    _, _, A0, A = oracle.hill_sum(spec, hills.centers, hills.heights, qq)
+    for ctx in (one, inc):
+        V, dV = abp.bias_eval(ctx, to_dev(qq), mode=abp.ABP_EVAL_GRID, prec=KAHAN)
+        check_bound("grid V, FP32 nodes", host(V), hq, A0, 1e-6)
+        check_bound("grid dV, FP32 nodes", host(dV), dhq, A, 1e-5)
 
 
 @pytest.mark.parametrize("ndim", [1, 3])
@@ -262,6 +278,13 @@ def test_grid_1d_3d(ndim, kernel):
     check_bound("grid V", host(V), hq, A0)
     check_bound("grid dV", host(dV), dhq, A)
     assert ncl > 0          # the queries reach outside the non-periodic range
+    # FP32 mirror: node values rounded to FP32; where a query's corners cancel, up to
+    # 2^-22 of the grid's largest entry (divided by the node spacing for dV) is rounding
+    V, dV = abp.bias_eval(ctx, to_dev(q), mode=abp.ABP_EVAL_GRID, prec=KAHAN)
+    dx = [(hi[i] - lo[i]) / (grid_n[i] if periodic[i] else grid_n[i] - 1) for i in range(ndim)]
+    ffloor = 2.0 ** -22 * np.abs(Ho).max() * max(1.0, max(dx)) ** ndim
+    check_bound("grid V, FP32 nodes", host(V), hq, A0, 1e-6, ffloor)
+    check_bound("grid dV, FP32 nodes", host(dV), dhq, A, 1e-5, ffloor * max(1.0, max(1.0 / h for h in dx)))
 
 
 # ---------------------------------------------------------------------------

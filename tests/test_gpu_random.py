@@ -101,3 +101,12 @@ def test_random_spec_parity(seed):
     gfloor = 1e-13 * gscale * gslope
     check_bound(f"seed {seed} grid V", host(V), Vg, sV, tolg, gfloor)
     check_bound(f"seed {seed} grid dV", host(dV), dVg, sG, tolg, gfloor[None, :] * max(1.0, max(1.0 / h for h in dx)))
+    # the FP32 mirror of the node arrays: node values rounded to FP32 (2^-24 of the
+    # grid's largest entry absorbs corners that cancel; value nodes enter the
+    # gradient divided by the node spacing); V at 1e-6, dV at 1e-5
+    V, dV = abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP32_KAHAN)
+    abp.abp_sync(ctx)
+    ffloor = 2.0 ** -22 * gscale * gslope
+    check_bound(f"seed {seed} grid V, FP32 nodes", host(V), Vg, sV, 1e-6, ffloor)
+    check_bound(f"seed {seed} grid dV, FP32 nodes", host(dV), dVg, sG, 1e-5,
+                ffloor[None, :] * max(1.0, max(1.0 / h for h in dx)))
