@@ -80,8 +80,37 @@ def timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+ONE_CORE_SCRIPT = """
+import sys, time
+import numpy as np
+sys.path.insert(0, {root!r})
+import oracle
+from paper_1609_09833_amd import workloads as W
+spec, hills, q = W.torsion_2d()
+idx = np.linspace(0, q.shape[1] - 1, {n}).astype(np.int64)
+t0 = time.perf_counter()
+oracle.hill_sum(spec, hills.centers, hills.heights, q[:, idx])
+print(time.perf_counter() - t0)
+"""
+
+
 def cpu_baseline(spec, hills, q, target_s=20.0):
-    """The FP64 oracle on an evenly spaced sample of the queries, all host cores."""
+    """The FP64 oracle on an evenly spaced sample of the queries, all host
+    cores; then one core (OMP_NUM_THREADS=1, a child process) on a smaller
+    sample."""
+    import subprocess
     import numpy as np
     import oracle
     nq = q.shape[1]
@@ -96,9 +125,20 @@ def cpu_baseline(spec, hills, q, target_s=20.0):
     oracle.hill_sum(spec, hills.centers, hills.heights, q[:, idx])
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of {nq} queries (evenly spaced) against all {hills.n} hills, FP64, "
-                      f"{dt:.1f} s"}
+    out = {"value": n / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} of {nq} queries (evenly spaced) against all {hills.n} hills, FP64, {dt:.1f} s",
+           "cpu_model": cpu_model()}
+    n1 = max(64, int(n / cores / 2))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", ONE_CORE_SCRIPT.format(root=ROOT, n=n1)], env=env,
+                           capture_output=True, text=True, timeout=300, check=True)
+        dt1 = float(r.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": n1 / dt1, "unit": "walker-steps/s", "cores": 1,
+                           "sample": f"{n1} of {nq} queries (evenly spaced), FP64, {dt1:.1f} s"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["one_core"] = {"error": str(e)[:200]}
+    return out
 
 
 def force_leg(abp, W, torch, args, stream):
@@ -271,9 +311,10 @@ def serving_leg(abp, W, torch, window_s=1.0):
             state["seeded"] = k + take
         torch.cuda.synchronize()
 
-    def server(budget, max_batch, streams):
+    def server(budget, max_batch, streams, mode=abp.ABP_EVAL_DIRECT):
         srv = abp.Server(ctx, wk.kinds, hbm_budget_bytes=budget, max_batch=max_batch, streams=streams,
-                         deposit_every=period, height0=1.2, height_decay=20000.0, max_pending=16384)
+                         deposit_every=period, height0=1.2, height_decay=20000.0, max_pending=16384,
+                         eval_mode=mode)
         for w in range(wk.nw):
             b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
             lens, idx, rx, ry, rz = W.walker_lists(wk, w)
@@ -327,6 +368,13 @@ def serving_leg(abp, W, torch, window_s=1.0):
     res["hist200k_plain_launches"] = run(srv, eng, "plain per-walker launches", n_win // 10, 130)
     res["hist200k_plain_launches_saturated"] = run(srv, eng, "plain saturated", n_win // 10, 131, req_rate=1e12)
     srv.close()
+    # GRID evaluation: the same requests read the 256 x 256 grid (kept current
+    # by the deposits' commits) instead of summing the 200k hills
+    srv, eng = server(budget, 1024, 2, abp.ABP_EVAL_GRID)
+    run(srv, eng, "grid warm-up (not reported)", n_win // 5, 139)
+    res["hist200k_budget2MiB_grid"] = run(srv, eng, "200k hills, 2 MiB, grid", n_win, 140)
+    res["hist200k_budget2MiB_grid_saturated"] = run(srv, eng, "grid saturated", n_win, 141, req_rate=1e12)
+    srv.close()
     ctx.close()
     return res
 
@@ -376,6 +424,35 @@ def grid_leg(abp, torch, args, stream, spec, nh, cen_d, hts_d, qd, V, dV):
     return extra
 
 
+def stress_direct_leg(abp, W, torch, n_queries=1 << 18):
+    """The precision-stress direct sum: 3-D CV space (a distance and two
+    torsions), 1,000,000 hills with heights log-uniform on [1e-4, 1]; the first
+    n_queries of its 4,194,304 queries (the kernel's rate does not depend on
+    the query count once the chip is full), FP32 + Kahan, FP32 naive and FP64."""
+    spec, hills, q = W.stress_3d()
+    q = q[:, :n_queries].copy()
+    ctx = abp.Context(spec, capacity=hills.n)
+    abp.bias_deposit(ctx, torch.as_tensor(hills.centers, device="cuda"), torch.as_tensor(hills.heights, device="cuda"))
+    qd = torch.as_tensor(q, device="cuda")
+    V = torch.empty(q.shape[1], dtype=torch.float32, device="cuda")
+    dV = torch.empty((3, q.shape[1]), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {"hills": hills.n, "queries": q.shape[1], "of_queries": 4 << 20}
+    for name, prec, steps in (("fp32_kahan", abp.ABP_PREC_FP32_KAHAN, 3), ("fp32_naive", abp.ABP_PREC_FP32_NAIVE, 3),
+                              ("fp64", abp.ABP_PREC_FP64, 2)):
+        def fn(prec=prec):
+            abp.bias_eval(ctx, qd, prec=prec, V=V, dVds=dV)
+        el, _ = timed(fn, steps, 1, stream)
+        pairs = q.shape[1] * hills.n * steps / el
+        out[name] = {"walker_steps_per_s": q.shape[1] * steps / el, "pairs_per_s": pairs,
+                     "ms_per_step": el / steps * 1e3}
+        log(f"bench: stress direct {name}: {pairs:.3e} pairs/s ({q.shape[1] * steps / el:.3e} walker-steps/s "
+            f"at 1M hills)")
+    abp.abp_sync(ctx)
+    ctx.close()
+    return out
+
+
 def stress_grid_leg(abp, W, torch):
     """The precision-stress grid: 1,000,000 Gaussian hills (a distance and two
     torsions) into the 128^3 FP64 grid, deposited twice into one context; the
@@ -412,8 +489,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (profiling)")
-    ap.add_argument("--only", choices=("headline", "grid", "stress-grid", "force", "latency", "serving",
-                                       "quantised"), default=None,
+    ap.add_argument("--only", choices=("headline", "grid", "stress-grid", "stress-direct", "force", "latency",
+                                       "serving", "quantised"), default=None,
                     help="run one leg only (profiling): the headline direct sum, its grid form, the "
                          "bias-force workload, single-walker latency, the quantised grid, the 128^3 "
                          "precision-stress grid build or serving")
@@ -445,6 +522,9 @@ def main():
         return
     if args.only == "stress-grid":
         print(json.dumps({"extra": {"stress_grid": stress_grid_leg(abp, W, torch)}}), flush=True)
+        return
+    if args.only == "stress-direct":
+        print(json.dumps({"extra": {"stress_direct": stress_direct_leg(abp, W, torch)}}), flush=True)
         return
     if args.only == "serving":
         print(json.dumps({"extra": {"serving": serving_leg(abp, W, torch)}}), flush=True)
@@ -535,6 +615,7 @@ def main():
     extra["single_walker_latency"] = latency_leg(abp, W, torch)
     extra["quantised_grid"] = quantised_leg(abp, W, torch)
     extra["stress_grid"] = stress_grid_leg(abp, W, torch)
+    extra["stress_direct"] = stress_direct_leg(abp, W, torch)
     if not args.no_serving:
         sv = serving_leg(abp, W, torch)
         head = sv["hist200k_budget2MiB"]
@@ -547,7 +628,11 @@ def main():
                           "plain_launch_capacity_req_per_s":
                               sv["hist200k_plain_launches_saturated"]["completed_req_per_s"],
                           "batched_capacity_req_per_s":
-                              sv["hist200k_budget2MiB_saturated"]["completed_req_per_s"]}
+                              sv["hist200k_budget2MiB_saturated"]["completed_req_per_s"],
+                          "grid_mode": {k: sv["hist200k_budget2MiB_grid"][k]
+                                        for k in ("p50_us", "p99_us", "p999_us", "completed_req_per_s")},
+                          "grid_mode_capacity_req_per_s":
+                              sv["hist200k_budget2MiB_grid_saturated"]["completed_req_per_s"]}
         extra["serving"] = sv
     out["extra"] = extra
     out["valu_issue"] = {"lane_ops_per_s_peak": VALU_LANE_OPS,

@@ -331,8 +331,11 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  * multiple of deposit_every deposits a hill at its CV value (height
  * height0 * exp(-k / height_decay) for history slot k) into a slot reserved
  * in batch-formation order; slots are committed, in order, once every earlier
- * slot is done. A request's result is bitwise the same whatever batch it
- * runs in. Forces are FP32; s, V and dV/ds FP64. */
+ * slot is done. Commits (and their grid deposits) run on one stream; with GRID
+ * evaluation a commit waits for the batches in flight and later batches wait
+ * for it, so a request reads exactly the grid of the hills of its version. A
+ * request's result is bitwise the same whatever batch it runs in. Forces are
+ * FP32; s, V and dV/ds FP64. */
 typedef struct abp_server abp_server;
 
 #define ABP_SERVER_BYTES_PER_ATOM 4   /* resident device state per CV atom: its FP32 mass */
@@ -348,6 +351,9 @@ typedef struct {
   double height_decay;       /* 0: constant height0 */
   int32_t cv_kind[3];        /* abp_cv_kind of CV a (a < ndim), same rules as abp_cv_desc.kind */
   int32_t max_pending;       /* requests submitted and not yet polled, >= 1 (bounds host staging) */
+  int32_t eval_mode;         /* abp_eval_mode: DIRECT sums the hills; GRID interpolates the context's
+                                grid (or looks it up in the quantised mode), which the commits of
+                                the requests' deposits keep current */
 } abp_server_desc;
 
 typedef struct {
@@ -390,7 +396,7 @@ typedef struct {
   int32_t admitted;          /* walkers admitted for it (their masses went with it) */
 } abp_server_batch;
 
-/* Create a server on a context (DIRECT sums only). Allocates the walker pool
+/* Create a server on a context (GRID evaluation needs a grid). Allocates the walker pool
  * (the budget), per-slot batch buffers sized for max_batch requests at the
  * history's capacity, and pinned host staging for max_pending requests once
  * the walkers are known (abp_server_start). ABP_E_INVAL for a bad descriptor,

@@ -64,7 +64,8 @@ class WalkersDesc(C.Structure):
 class ServerDesc(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32),
                 ("deposit_every", C.c_int32), ("prec", C.c_int32), ("height0", C.c_double),
-                ("height_decay", C.c_double), ("cv_kind", C.c_int32 * 3), ("max_pending", C.c_int32)]
+                ("height_decay", C.c_double), ("cv_kind", C.c_int32 * 3), ("max_pending", C.c_int32),
+                ("eval_mode", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -389,12 +390,14 @@ class Server:
     force on them."""
 
     def __init__(self, ctx, kinds, hbm_budget_bytes=1 << 30, max_batch=1024, streams=2, deposit_every=0,
-                 prec=ABP_PREC_FP32_KAHAN, height0=0.0, height_decay=0.0, max_pending=4096):
+                 prec=ABP_PREC_FP32_KAHAN, height0=0.0, height_decay=0.0, max_pending=4096,
+                 eval_mode=ABP_EVAL_DIRECT):
         self.ctx = ctx
         d = ServerDesc()
         d.hbm_budget_bytes, d.max_batch, d.streams = int(hbm_budget_bytes), int(max_batch), int(streams)
         d.deposit_every, d.prec = int(deposit_every), int(prec)
         d.height0, d.height_decay, d.max_pending = float(height0), float(height_decay), int(max_pending)
+        d.eval_mode = int(eval_mode)
         for i in range(3):
             d.cv_kind[i] = int(kinds[i]) if i < len(kinds) else 0
         self.desc = d

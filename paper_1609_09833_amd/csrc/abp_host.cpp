@@ -549,6 +549,7 @@ CtxView ctx_view(abp_ctx* ctx) {
   CtxView v;
   v.K = ctx->K;
   v.H = ctx->hist();
+  v.grid = ctx->grid;
   v.err = ctx->err;
   v.device = ctx->device;
   return v;

@@ -13,14 +13,8 @@ namespace abp {
 constexpr int kBlock = 256;      // threads per block for every kernel
 constexpr int kTile32 = 1024;    // hills per LDS tile in the FP32 direct sum (16 KiB)
 constexpr int kTile64 = 512;     // hills per LDS tile in the FP64 direct sum (16 KiB)
-#ifndef ABP_CHUNK
-#define ABP_CHUNK 32
-#endif
-#ifndef ABP_Q2D
-#define ABP_Q2D 2
-#endif
-constexpr int kChunk = ABP_CHUNK; // hills summed plainly before each compensated (Kahan) step
-constexpr int kQ2D = ABP_Q2D;     // queries per thread in the 2-D/3-D FP32 direct sum
+constexpr int kChunk = 32;       // hills summed plainly before each compensated (Kahan) step
+constexpr int kQ2D = 2;          // queries per thread in the 2-D/3-D FP32 direct sum
 
 // Largest magnitude of a non-periodic FP32 working word (see Consts).
 constexpr double kFixLimit = 1073741823.0;   // 2^30 - 1

@@ -9,6 +9,7 @@ namespace abp {
 struct CtxView {
   Consts K;
   HistView H;
+  const double* grid;              // the FP64 node arrays, or NULL
   int32_t* err;
   int device;
 };

@@ -68,8 +68,8 @@ constexpr int64_t kFusedMaxHills = 16384;
 // one or two walkers (measured: 100,000 hills, one walker, 25.9 -> 21.9 us);
 // for the serving loop's batches of a few walkers on concurrent streams the
 // redundant CV gathers cost more than the two launches they save (p50 at
-// 200,000 hills 90 -> 131 us). kChainCounters bounds the batches that the
-// ABP_FORCE_SHAPE=chain override can send through it.
+// 200,000 hills 90 -> 131 us). kChainCounters bounds the batches that a
+// fixed chained shape (abp_set_force_shape) can send through it.
 constexpr int64_t kChainMaxWalkers = 2;
 constexpr int64_t kChainCounters = 64;
 
@@ -880,10 +880,7 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
 // walkers; a lane whose walker sees fewer hills masks the rest. The walkers'
 // CV values come from a compact [D][nw] array (coalesced).
 // ---------------------------------------------------------------------------
-#ifndef ABP_SUM_CPW
-#define ABP_SUM_CPW 1
-#endif
-constexpr int kChunksPerWave = ABP_SUM_CPW;   // consecutive chunks one wave sums (its fixed costs amortised)
+constexpr int kChunksPerWave = 1;   // consecutive chunks one wave sums
 
 template <int D, int PMASK, int KERN, bool FP64>
 __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {

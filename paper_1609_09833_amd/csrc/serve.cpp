@@ -101,6 +101,7 @@ struct Slot {
   int64_t version = 0;
   double t_formed = 0.0, t_launched = 0.0;
   int32_t admitted = 0;
+  int64_t commit_seen = 0;           // commits this slot's stream has waited for (GRID)
   std::vector<int32_t> reqs;         // records
   std::vector<int64_t> dep_slots;    // history slot per request or -1
   char* h_desc = nullptr;            // pinned descriptor, then the staged masses
@@ -162,6 +163,8 @@ struct abp_server {
   std::vector<Slot> slots;
   std::deque<int> launch_order;      // busy slots in launch order
   hipStream_t commit_stream = nullptr;
+  hipEvent_t commit_done = nullptr;  // recorded after every commit (GRID evaluation waits for it)
+  int64_t commit_seq = 0;            // commits issued
   std::map<int64_t, bool> dep_done;  // reserved slot -> done
   int64_t resident = 0;
   // request staging: max_pending records, each with a fixed strip of the
@@ -280,8 +283,16 @@ abp_status commit_prefix(abp_server* S) {
   }
   const int64_t before = abp_num_hills(S->ctx);
   if (upto > before) {
+    const bool grid = S->desc.eval_mode == ABP_EVAL_GRID;
+    if (grid)          // batches in flight read the grid of their own version
+      for (const int k : S->launch_order)
+        SRV_TRY(hipStreamWaitEvent(S->commit_stream, S->slots[k].done, 0));
     const abp_status st = abp_commit(S->ctx, upto, S->commit_stream);
     if (st != ABP_OK) return st;
+    if (grid) {
+      SRV_TRY(hipEventRecord(S->commit_done, S->commit_stream));
+      S->commit_seq++;
+    }
     std::lock_guard<std::mutex> lk(S->mu_stats);
     S->stats.deposits += upto - before;
   }
@@ -348,6 +359,11 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
     sl.dep_slots.push_back(slot);
   }
   sl.nb = nb;
+  const bool grid = S->desc.eval_mode == ABP_EVAL_GRID;
+  if (grid && sl.commit_seen != S->commit_seq) {     // the grid must hold every hill of the version
+    SRV_TRY(hipStreamWaitEvent(sl.stream, S->commit_done, 0));
+    sl.commit_seen = S->commit_seq;
+  }
   SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float), hipMemcpyHostToDevice,
                          sl.stream));
   const int64_t M = S->block;
@@ -385,6 +401,8 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
   A.dVds = sl.m_out + (S->ncv + 1) * nb;
   A.prec = S->desc.prec;
   A.shape = shape;
+  A.use_grid = grid ? 1 : 0;
+  A.grid = S->cv.grid;
   A.err = S->cv.err;
   SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
   SRV_TRY(hipEventRecord(sl.done, sl.stream));
@@ -615,7 +633,7 @@ abp_status warm_up(abp_server* S) {
   std::memset(S->arena + R.arena_off, 0, sizeof(float) * 6 * (size_t)S->block);
   const int32_t wid = 0;
   Slot& sl = S->slots[0];
-  const int nshapes = abp_num_hills(S->ctx) > 0 ? 3 : 1;
+  const int nshapes = (abp_num_hills(S->ctx) > 0 && S->desc.eval_mode != ABP_EVAL_GRID) ? 3 : 1;
   const int32_t shapes[3] = {ABP_SHAPE_FUSED, ABP_SHAPE_SPLIT, ABP_SHAPE_CHAIN};
   for (int k = 0; k < nshapes; ++k) {
     const int32_t shape = shapes[k];
@@ -651,6 +669,8 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
       !std::isfinite(desc->height_decay))
     return sfail(ABP_E_INVAL, "bad deposit height law");
   if (desc->max_pending < 1 || desc->max_pending > (1 << 24)) return sfail(ABP_E_INVAL, "max_pending must be 1..2^24");
+  if (desc->eval_mode != ABP_EVAL_DIRECT && desc->eval_mode != ABP_EVAL_GRID)
+    return sfail(ABP_E_INVAL, "unknown eval mode");
   abp_server* S = new (std::nothrow) abp_server();
   if (!S) return sfail(ABP_E_NOMEM, "host allocation failed");
   S->t0 = std::chrono::steady_clock::now();
@@ -671,6 +691,10 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
     }
     S->kind[a] = k;
   }
+  if (desc->eval_mode == ABP_EVAL_GRID && !S->cv.grid) {
+    delete S;
+    return sfail(ABP_E_INVAL, "GRID evaluation needs a context with a grid");
+  }
   if (hipSetDevice(S->cv.device) != hipSuccess) {
     delete S;
     return sfail(ABP_E_DEVICE, "cannot select the context's device");
@@ -685,7 +709,8 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
   const int64_t B = desc->max_batch;
   const size_t ws = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
   S->slots.resize(desc->streams);
-  bool good = hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) == hipSuccess;
+  bool good = hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&S->commit_done, hipEventDisableTiming) == hipSuccess;
   for (auto& sl : S->slots) {
     good = good && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
@@ -740,6 +765,7 @@ abp_status abp_server_destroy(abp_server* S) {
     (void)hipStreamSynchronize(S->commit_stream);
     (void)hipStreamDestroy(S->commit_stream);
   }
+  if (S->commit_done) (void)hipEventDestroy(S->commit_done);
   if (S->arena) (void)hipHostFree(S->arena);
   if (S->d_lidx) (void)hipFree(S->d_lidx);
   if (S->d_rx) (void)hipFree(S->d_rx);
@@ -852,7 +878,10 @@ abp_status abp_server_start(abp_server* S) {
   for (auto& sl : S->slots) {
     SRV_TRY(hipStreamSynchronize(sl.stream));
     sl.busy = false;
+    sl.commit_seen = 0;
   }
+  SRV_TRY(hipStreamSynchronize(S->commit_stream));
+  S->commit_seq = 0;
   abp_status st = size_buffers(S);
   if (st != ABP_OK) return st;
   st = warm_up(S);

@@ -56,8 +56,8 @@ int main(void) {
          offsetof(abp_bias_desc, wt_dT));
   printf("%zu %zu %zu\\n", sizeof(abp_cv_desc), offsetof(abp_cv_desc, list_off), offsetof(abp_cv_desc, ref_z));
   printf("%zu %zu %zu\\n", sizeof(abp_walkers), offsetof(abp_walkers, x), offsetof(abp_walkers, fz));
-  printf("%zu %zu %zu\\n", sizeof(abp_server_desc), offsetof(abp_server_desc, max_pending),
-         offsetof(abp_server_desc, cv_kind));
+  printf("%zu %zu %zu %zu\\n", sizeof(abp_server_desc), offsetof(abp_server_desc, max_pending),
+         offsetof(abp_server_desc, cv_kind), offsetof(abp_server_desc, eval_mode));
   printf("%zu %zu\\n", sizeof(abp_server_stats), offsetof(abp_server_stats, wall_seconds));
   printf("%d\\n", ABP_SERVER_BYTES_PER_ATOM);
   printf("%zu %zu %zu %zu %zu\\n", sizeof(abp_server_result), offsetof(abp_server_result, walker),
@@ -77,7 +77,8 @@ int main(void) {
                        abp.BiasDesc.kT.offset, abp.BiasDesc.quantize.offset, abp.BiasDesc.wt_dT.offset]
     assert vals[1] == [C.sizeof(abp.CvDesc), abp.CvDesc.list_off.offset, abp.CvDesc.ref_z.offset]
     assert vals[2] == [C.sizeof(abp.WalkersDesc), abp.WalkersDesc.x.offset, abp.WalkersDesc.fz.offset]
-    assert vals[3] == [C.sizeof(abp.ServerDesc), abp.ServerDesc.max_pending.offset, abp.ServerDesc.cv_kind.offset]
+    assert vals[3] == [C.sizeof(abp.ServerDesc), abp.ServerDesc.max_pending.offset, abp.ServerDesc.cv_kind.offset,
+                       abp.ServerDesc.eval_mode.offset]
     assert vals[4] == [C.sizeof(abp.ServerStats), abp.ServerStats.wall_seconds.offset]
     assert vals[5] == [abp.ABP_SERVER_BYTES_PER_ATOM]
     R, B = abp.SERVER_RESULT, abp.SERVER_BATCH

@@ -71,10 +71,10 @@ def _cv_budget(lib, ncv, fraction):
     return lib.ABP_SERVER_BYTES_PER_ATOM * int(ncv.astype(np.int64).sum() * fraction)
 
 
-def _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version):
+def _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version, H=None):
     """The oracle's bias force for walker w with its CV atoms at xyz ([3][n_cv]),
-    over the first `version` hills: (s, V, dV, forces on the CV atoms [3][n_cv],
-    A0, A, per-atom force scale [3][n_cv])."""
+    over the first `version` hills (or interpolated from their grid H): (s, V,
+    dV, forces on the CV atoms [3][n_cv], A0, A, per-atom force scale [3][n_cv])."""
     from oracle import bias_eval, bias_force
     b, n = int(wk.atom_base[w]), int(wk.n_atoms[w])
     x, y, z = (np.asarray(a[b:b + n], dtype=np.float32).copy() for a in (wk.x, wk.y, wk.z))
@@ -83,7 +83,7 @@ def _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version):
     one = W.single_walker(wk, w, x, y, z)
     zero = np.zeros(n)
     c, h = centers[:, :version], heights[:version]
-    s, V, dV, fx, fy, fz, status = bias_force(spec, c, h, one, zero, zero, zero)
+    s, V, dV, fx, fy, fz, status = bias_force(spec, c, h, one, zero, zero, zero, use_grid=H is not None, H=H)
     assert status[0] == 0
     _, _, sA0, sA = bias_eval(spec, c, h, s)
     F = np.stack([fx[atoms], fy[atoms], fz[atoms]])
@@ -100,18 +100,22 @@ def _wrap(d):
     return (d + np.pi) % (2 * np.pi) - np.pi
 
 
-def _check_request(name, spec, centers, heights, wk, srv, r, w, xyz, version, s, V, dV, F):
+def _check_request(name, spec, centers, heights, wk, srv, r, w, xyz, version, s, V, dV, F, H=None):
+    """One served request against the oracle: the direct sum at 1e-5, or (H
+    given) the interpolation of the grid of its version at 1e-9 (forces, being
+    FP32, at 1e-6)."""
     atoms = srv.walker_atoms(w)
-    s_o, V_o, dV_o, F_o, A0, A, fscale = _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version)
+    s_o, V_o, dV_o, F_o, A0, A, fscale = _oracle_request(spec, centers, heights, wk, w, atoms, xyz, version, H)
     ds = s - s_o
     for a in range(spec.ndim):
         if spec.periodic[a]:
             ds[a] = _wrap(ds[a])
     assert np.abs(ds).max() < 1e-12, (name, r, ds)
-    rv = check_bound(f"{name} V (request {r})", np.array([V]), np.array([V_o]), np.array([A0]))
-    rg = check_bound(f"{name} dV/ds (request {r})", dV, dV_o, A)
+    tol = 1e-5 if H is None else 1e-9
+    rv = check_bound(f"{name} V (request {r})", np.array([V]), np.array([V_o]), np.array([A0]), tol)
+    rg = check_bound(f"{name} dV/ds (request {r})", dV, dV_o, A, tol)
     # forces are FP32: at least their output rounding
-    rf = check_bound(f"{name} forces (request {r})", F.reshape(3, -1), F_o, fscale, tol=1e-5, floor=0.0)
+    rf = check_bound(f"{name} forces (request {r})", F.reshape(3, -1), F_o, fscale, tol=max(tol, 1e-6), floor=0.0)
     return max(rv, rg, rf)
 
 
@@ -181,15 +185,64 @@ def test_serving_with_deposits_matches_oracle(lib, drv):
     ctx.close()
 
 
+def test_serving_grid_with_deposits_matches_oracle(lib, drv):
+    """GRID evaluation: batches read the context's grid while the commits of
+    the requests' deposits update it on their own stream; every request must
+    equal the oracle's interpolation of the grid of exactly its version."""
+    import dataclasses
+    import oracle
+    import torch
+    spec, hills = W.ligand_pocket_hills(seed=3, n_hills=1000)
+    spec = dataclasses.replace(spec, grid_n=(64, 64))
+    wk = W.ligand_pocket_walkers(seed=5, n_walkers=N_WALKERS)
+    ctx = lib.Context(spec, hills.n + 1024)
+    lib.bias_deposit(ctx, torch.tensor(hills.centers, device="cuda"), torch.tensor(hills.heights, device="cuda"))
+    torch.cuda.synchronize()
+    probe = lib.Server(ctx, wk.kinds)
+    ncv = _register(probe, wk)
+    probe.close()
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=_cv_budget(lib, ncv, 1 / 3), max_batch=16, streams=2,
+                     deposit_every=3, height0=1.2, height_decay=20000.0, eval_mode=lib.ABP_EVAL_GRID)
+    _register(srv, wk)
+    eng = drv.Engines(srv, wk)
+    srv.start()
+    t, w, step = W.serving_requests(seed=7, n_walkers=N_WALKERS, rate=5_000.0, n_requests=300)
+    out = drv.replay(srv, eng, w, step, t, AMP)
+    srv.stop()
+    st = srv.stats()
+    assert st["completed"] == len(t) and st["evictions"] > 0 and st["deposits"] > 0
+    dep = out["deposit_slot"]
+    assert np.array_equal(dep >= 0, (step % 3) == 0)
+    centers, heights = lib.abp_hills_export(ctx)
+    grids = {}
+    worst = 0.0
+    for r in range(len(t)):
+        v = int(out["version"][r])
+        if v not in grids:
+            grids[v] = oracle.grid_all(spec, centers[:, :v], heights[:v])
+        o, k3 = int(out["offset"][r]), 3 * int(eng.n_cv[w[r]])
+        worst = max(worst, _check_request("grid served", spec, centers, heights, wk, srv, r, int(w[r]),
+                                          out["positions"][o:o + k3], v, out["s"][:, r], out["V"][r],
+                                          out["dVds"][:, r], out["forces"][o:o + k3], H=grids[v]))
+    print(f"grid-served requests: {len(grids)} versions, worst error / bound {worst:.3e}")
+    H = lib.abp_grid_export(ctx)
+    Ho = oracle.grid_all(spec, centers, heights)
+    np.testing.assert_allclose(H, Ho, rtol=1e-9, atol=1e-12 * np.abs(Ho).max())
+    srv.close()
+    ctx.close()
+
+
 def test_serving_alone_equals_in_the_mix(lib, drv):
     """Without deposits a request's s, V, dV/ds and forces are bitwise the same
     whether it ran alone (one request per launch, one stream) or inside mixed
-    batches on three streams."""
+    batches on three streams, with DIRECT and with GRID evaluation."""
     spec, hills, wk, ctx = _setup(lib)
     t, w, step = W.serving_requests(seed=2, n_walkers=N_WALKERS, rate=100_000.0, n_requests=400)
     res = []
-    for mb, ns in ((1, 1), (64, 3)):
-        srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=mb, streams=ns, deposit_every=0)
+    for mb, ns, mode in ((1, 1, lib.ABP_EVAL_DIRECT), (64, 3, lib.ABP_EVAL_DIRECT), (1, 1, lib.ABP_EVAL_GRID),
+                         (64, 3, lib.ABP_EVAL_GRID)):
+        srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=1 << 30, max_batch=mb, streams=ns, deposit_every=0,
+                         eval_mode=mode)
         _register(srv, wk)
         eng = drv.Engines(srv, wk)
         srv.start()
@@ -199,14 +252,15 @@ def test_serving_alone_equals_in_the_mix(lib, drv):
         out["stats"] = srv.stats()
         res.append(out)
         srv.close()
-    alone, mix = res
-    assert alone["stats"]["max_batch_seen"] == 1
-    assert mix["stats"]["batches"] < alone["stats"]["batches"]
-    for k in ("s", "V", "dVds", "forces", "positions"):
-        assert np.array_equal(alone[k], mix[k]), k
-    assert np.all(np.isfinite(alone["forces"]))
-    assert np.all(alone["version"] == N_HILLS) and np.all(mix["version"] == N_HILLS)
-    assert np.all(alone["deposit_slot"] == -1)
+    for alone, mix in (res[:2], res[2:]):
+        assert alone["stats"]["max_batch_seen"] == 1
+        assert mix["stats"]["batches"] < alone["stats"]["batches"]
+        for k in ("s", "V", "dVds", "forces", "positions"):
+            assert np.array_equal(alone[k], mix[k]), k
+        assert np.all(np.isfinite(alone["forces"]))
+        assert np.all(alone["version"] == N_HILLS) and np.all(mix["version"] == N_HILLS)
+        assert np.all(alone["deposit_slot"] == -1)
+    assert not np.array_equal(res[0]["V"], res[2]["V"])          # direct sum and grid differ
     ctx.close()
 
 
@@ -291,6 +345,12 @@ def test_serving_rejects_bad_input(lib):
         lib.Server(ctx, wk.kinds, max_batch=0)
     with pytest.raises(lib.AbpError):
         lib.Server(ctx, wk.kinds, max_pending=0)
+    import dataclasses
+    import torch
+    nogrid = lib.Context(dataclasses.replace(spec, grid_n=(0, 0)), 16)
+    with pytest.raises(lib.AbpError):
+        lib.Server(nogrid, wk.kinds, eval_mode=lib.ABP_EVAL_GRID)   # GRID needs a grid
+    nogrid.close()
     small = lib.Server(ctx, wk.kinds, hbm_budget_bytes=lib.ABP_SERVER_BYTES_PER_ATOM * 100)
     b, n = int(wk.atom_base[0]), int(wk.n_atoms[0])
     lens, idx, rx, ry, rz = W.walker_lists(wk, 0)
