@@ -352,8 +352,13 @@ typedef struct {
   int32_t cv_kind[3];        /* abp_cv_kind of CV a (a < ndim), same rules as abp_cv_desc.kind */
   int32_t max_pending;       /* requests submitted and not yet polled, >= 1 (bounds host staging) */
   int32_t eval_mode;         /* abp_eval_mode: DIRECT sums the hills; GRID interpolates the context's
-                                grid (or looks it up in the quantised mode), which the commits of
-                                the requests' deposits keep current */
+                                grid (or looks it up in the quantised mode). GRID keeps a second
+                                copy of the node arrays (device memory of the grid's size): a
+                                request reads the copy that holds every hill up to the version it
+                                reports, while the commits of deposits are added to the other copy,
+                                so requests never wait for a commit. While the server runs the
+                                context's own grid may lag its history; abp_server_stop brings it
+                                up to date. Needs a context with a grid. */
 } abp_server_desc;
 
 typedef struct {
@@ -458,7 +463,7 @@ abp_status abp_server_get_stats(abp_server* srv, abp_server_stats* out);
 
 /* Copy up to max batch records (the most recent ones, oldest first) of the
  * run since the last start into out; *n receives the number copied. The
- * server keeps the last 2^20 batches. */
+ * server keeps the last 2^18 batches (262,144). */
 abp_status abp_server_trace(abp_server* srv, abp_server_batch* out, int64_t max, int64_t* n);
 
 /* Static message for a status code. */

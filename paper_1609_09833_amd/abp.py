@@ -488,7 +488,7 @@ class Server:
         _check(lib.abp_server_get_stats(self.handle, C.byref(s)))
         return {name: getattr(s, name) for name, _ in ServerStats._fields_}
 
-    def trace(self, max_batches=1 << 20):
+    def trace(self, max_batches=1 << 18):
         """Batch records of the run (SERVER_BATCH fields), oldest first."""
         import numpy as np
         out = np.zeros(max(int(max_batches), 1), dtype=SERVER_BATCH)

@@ -34,8 +34,7 @@ struct abp_ctx {
   size_t scratch_bytes = 0;
   void* fws = nullptr;                // bias_force: CV state, atom lists, partial sums
   size_t fws_bytes = 0;
-  void* wt_buf = nullptr;             // bias_deposit: bias at new centres (well-tempered heights)
-  size_t wt_bytes = 0;
+  void* wt_buf = nullptr;             // bias_deposit (well-tempered): kWtChunk centres, their V and dV/ds
   int32_t force_shape = ABP_SHAPE_AUTO;
 
   HistView hist() const {
@@ -225,6 +224,12 @@ abp::ForceArgs force_args(const abp_ctx* ctx, const abp_cv_desc* cv, const abp_w
   return A;
 }
 
+// Well-tempered deposits run in chunks of this many hills through a buffer
+// allocated with the context (so bias_deposit allocates nothing for them).
+constexpr int64_t kWtChunk = 16384;
+
+size_t wt_buffer_bytes(int ndim) { return (size_t)kWtChunk * (2 * ndim + 1) * sizeof(double); }
+
 abp_status grow_scratch(abp_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->scratch_bytes) return ABP_OK;
   if (ctx->scratch) {
@@ -258,14 +263,20 @@ abp_status force_workspace(abp_ctx* ctx, int64_t nw, int nbw) {
 }
 
 // Adds committed hills [k0, k1) to the grid.
-abp_status grid_add(abp_ctx* ctx, int64_t k0, int64_t k1, hipStream_t stream) {
-  if (!ctx->grid || k1 <= k0) return ABP_OK;
+// Adds committed hills [k0, k1) to the node arrays `grid` and refreshes the
+// FP32 mirror `grid32` (when not NULL).
+abp_status grid_add_to(abp_ctx* ctx, double* grid, float* grid32, int64_t k0, int64_t k1, hipStream_t stream) {
+  if (!grid || k1 <= k0) return ABP_OK;
   const size_t need = abp::grid_deposit_scratch_bytes(ctx->K, k1 - k0);
   abp_status st = grow_scratch(ctx, need);
   if (st != ABP_OK) return st;
-  HIP_TRY(abp::launch_grid_deposit(ctx->K, ctx->hist(), k0, k1, ctx->grid, need ? ctx->scratch : nullptr, stream));
-  HIP_TRY(abp::launch_grid_mirror(ctx->K, ctx->grid, ctx->grid32, stream));
+  HIP_TRY(abp::launch_grid_deposit(ctx->K, ctx->hist(), k0, k1, grid, need ? ctx->scratch : nullptr, stream));
+  if (grid32) HIP_TRY(abp::launch_grid_mirror(ctx->K, grid, grid32, stream));
   return ABP_OK;
+}
+
+abp_status grid_add(abp_ctx* ctx, int64_t k0, int64_t k1, hipStream_t stream) {
+  return grid_add_to(ctx, ctx->grid, ctx->grid32, k0, k1, stream);
 }
 
 void free_all(abp_ctx* ctx) {
@@ -312,6 +323,7 @@ abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out) {
               hipMalloc(&ctx->rec32, sizeof(int4) * cap) == hipSuccess &&
               hipMalloc(&ctx->err, sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&ctx->clamped, sizeof(unsigned long long)) == hipSuccess;
+  if (good && desc->wt_dT > 0.0) good = hipMalloc(&ctx->wt_buf, wt_buffer_bytes(desc->ndim)) == hipSuccess;
   if (good && ctx->K.nodes > 0)
     good = hipMalloc(&ctx->grid, sizeof(double) * (size_t)(ctx->K.nodes << desc->ndim)) == hipSuccess &&
            hipMalloc(&ctx->grid32, sizeof(float) * abp::grid_mirror_floats(ctx->K)) == hipSuccess;
@@ -360,27 +372,31 @@ abp_status bias_deposit(abp_ctx* ctx, int64_t n, abp_dtype dtype, const void* ce
     return fail(ABP_E_CAPACITY, "history capacity %lld exceeded", (long long)ctx->desc.capacity);
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  const void* vbias = nullptr;
-  if (ctx->desc.wt_dT > 0.0 && ctx->committed > 0) {
-    // well-tempered heights: the bias at each new centre, FP64 direct sum over
-    // the hills committed so far (V and dV/ds in the centres' dtype)
-    const size_t esz = dtype == ABP_F64 ? sizeof(double) : sizeof(float);
-    const size_t need = (size_t)n * (1 + ctx->desc.ndim) * esz;
-    if (need > ctx->wt_bytes) {
-      if (ctx->wt_buf) (void)hipFree(ctx->wt_buf);
-      ctx->wt_buf = nullptr;
-      ctx->wt_bytes = 0;
-      if (hipMalloc(&ctx->wt_buf, need) != hipSuccess) return fail(ABP_E_NOMEM, "cannot allocate %zu bytes", need);
-      ctx->wt_bytes = need;
-    }
-    char* buf = static_cast<char*>(ctx->wt_buf);
-    HIP_TRY(abp::launch_direct_sum(ctx->K, ctx->hist(), ctx->committed, ABP_PREC_FP64, n, dtype == ABP_F64 ? 1 : 0,
-                                   centers, buf, buf + (size_t)n * esz, s));
-    vbias = buf;
-  }
-  HIP_TRY(abp::launch_hist_append(ctx->K, ctx->hist(), ctx->committed, n, dtype == ABP_F64 ? 1 : 0,
-                                  centers, heights, vbias, ctx->err, s));
   const int64_t k0 = ctx->committed;
+  if (ctx->desc.wt_dT > 0.0 && k0 > 0) {
+    // well-tempered heights: the bias at each new centre, an FP64 direct sum
+    // over the k0 hills committed before this call (not over earlier chunks of
+    // it), in the centres' dtype. Per chunk: copy its centres out of the
+    // [ndim][n] array, sum, append; the stream orders the buffer's reuse.
+    const int nd = ctx->desc.ndim;
+    const size_t esz = dtype == ABP_F64 ? sizeof(double) : sizeof(float);
+    char* buf = static_cast<char*>(ctx->wt_buf);
+    for (int64_t off = 0; off < n; off += kWtChunk) {
+      const int64_t c = std::min<int64_t>(kWtChunk, n - off);
+      char* cen = buf;
+      char* vb = buf + (size_t)c * nd * esz;
+      char* db = vb + (size_t)c * esz;
+      HIP_TRY(hipMemcpy2DAsync(cen, (size_t)c * esz, static_cast<const char*>(centers) + (size_t)off * esz,
+                               (size_t)n * esz, (size_t)c * esz, (size_t)nd, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(abp::launch_direct_sum(ctx->K, ctx->hist(), k0, ABP_PREC_FP64, c, dtype == ABP_F64 ? 1 : 0, cen, vb,
+                                     db, s));
+      HIP_TRY(abp::launch_hist_append(ctx->K, ctx->hist(), k0 + off, c, dtype == ABP_F64 ? 1 : 0, cen,
+                                      static_cast<const char*>(heights) + (size_t)off * esz, vb, ctx->err, s));
+    }
+  } else {
+    HIP_TRY(abp::launch_hist_append(ctx->K, ctx->hist(), k0, n, dtype == ABP_F64 ? 1 : 0, centers, heights,
+                                    nullptr, ctx->err, s));
+  }
   ctx->committed += n;
   ctx->reserved = ctx->committed;
   abp_status st = grid_add(ctx, k0, ctx->committed, s);
@@ -550,6 +566,8 @@ CtxView ctx_view(abp_ctx* ctx) {
   v.K = ctx->K;
   v.H = ctx->hist();
   v.grid = ctx->grid;
+  v.grid32 = ctx->grid32;
+  v.grid_doubles = ctx->grid ? (size_t)(ctx->K.nodes << ctx->desc.ndim) : 0;
   v.err = ctx->err;
   v.device = ctx->device;
   return v;
@@ -598,6 +616,21 @@ abp_status ctx_reserve_commit(abp_ctx* ctx, int64_t n) {
   if (!ctx->grid || n <= 0) return ok();
   DeviceGuard guard(ctx->device);
   return grow_scratch(ctx, abp::grid_deposit_scratch_bytes(ctx->K, n));
+}
+
+abp_status ctx_commit_hills(abp_ctx* ctx, int64_t upto) {
+  if (upto < ctx->committed || upto > ctx->reserved)
+    return fail(ABP_E_INVAL, "commit target %lld outside [%lld, %lld]", (long long)upto,
+                (long long)ctx->committed, (long long)ctx->reserved);
+  ctx->committed = upto;
+  return ok();
+}
+
+abp_status ctx_grid_add(abp_ctx* ctx, double* grid, float* grid32, int64_t k0, int64_t k1, hipStream_t stream) {
+  if (k0 < 0 || k1 > ctx->committed) return fail(ABP_E_INVAL, "hills [%lld, %lld) are not committed", (long long)k0,
+                                                 (long long)k1);
+  DeviceGuard guard(ctx->device);
+  return grid_add_to(ctx, grid, grid32, k0, k1, stream);
 }
 
 abp_status set_error(abp_status st, const char* msg) {

@@ -101,6 +101,23 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, const float* gr
 size_t grid_mirror_floats(const Consts& K);
 hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, hipStream_t stream);
 
+// The per-walker fields of a batch of up to kInlineWalkers walkers, carried
+// in the kernel arguments (the serving loop's small batches), so that no copy
+// of a descriptor has to precede the launch. Used when ForceArgs::inl_n > 0,
+// in place of list_beg/list_len, atom_base, n_atoms, mass_base, stage_off,
+// deposit_slot (-1: no deposit) and deposit_height.
+constexpr int kInlineWalkers = 16;
+struct InlineDesc {
+  int64_t atom_base[kInlineWalkers];
+  int64_t mass_base[kInlineWalkers];
+  int64_t stage_off[kInlineWalkers];
+  int64_t deposit_slot[kInlineWalkers];
+  double deposit_height[kInlineWalkers];
+  int32_t n_atoms[kInlineWalkers];
+  int32_t list_beg[6][kInlineWalkers];
+  int32_t list_len[6][kInlineWalkers];
+};
+
 struct ForceArgs {
   int32_t ncv;
   int32_t kind[3];
@@ -143,6 +160,14 @@ struct ForceArgs {
   int32_t prec;                    // abp_prec
   const double* grid;
   int32_t* err;
+  // Completion words (NULL: none): when walker w's step is done (outputs,
+  // deposit, forces all stored and released at system scope), the block that
+  // finished it stores done_seq to done_flag[w]. For host-mapped words that a
+  // host thread polls instead of waiting on a stream event.
+  uint32_t* done_flag;
+  uint32_t done_seq;
+  int32_t inl_n;                   // > 0: nw, and the per-walker fields are in inl
+  InlineDesc inl;
 };
 
 // A walker's direct sum in bias_force over nvis hills is split into chunks of

@@ -109,7 +109,10 @@ struct FArgs {
 };
 
 __device__ __forceinline__ void list_bounds(const ForceArgs& A, int64_t w, int q, int& b, int& n) {
-  if (A.list_beg) {
+  if (A.inl_n) {
+    b = A.inl.list_beg[q][w];
+    n = A.inl.list_len[q][w];
+  } else if (A.list_beg) {
     b = A.list_beg[(int64_t)q * A.nw + w];
     n = A.list_len[(int64_t)q * A.nw + w];
   } else {
@@ -117,6 +120,26 @@ __device__ __forceinline__ void list_bounds(const ForceArgs& A, int64_t w, int q
     b = off[w];
     n = off[w + 1] - off[w];
   }
+}
+
+// Per-walker fields, from the kernel arguments for an inline batch.
+__device__ __forceinline__ int64_t w_atom_base(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.atom_base[w] : A.atom_base[w];
+}
+__device__ __forceinline__ int64_t w_mass_base(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.mass_base[w] : (A.mass_base ? A.mass_base[w] : A.atom_base[w]);
+}
+__device__ __forceinline__ int64_t w_stage_off(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.stage_off[w] : (A.stage_off ? A.stage_off[w] : -1);
+}
+__device__ __forceinline__ int32_t w_n_atoms(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.n_atoms[w] : A.n_atoms[w];
+}
+__device__ __forceinline__ int64_t w_deposit_slot(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.deposit_slot[w] : (A.deposit_slot ? A.deposit_slot[w] : -1);
+}
+__device__ __forceinline__ double w_deposit_height(const ForceArgs& A, int64_t w) {
+  return A.inl_n ? A.inl.deposit_height[w] : (A.deposit_height ? A.deposit_height[w] : 1.0);
 }
 
 __device__ __forceinline__ int64_t walker_nvis(const FArgs& F, int64_t w) {
@@ -191,6 +214,16 @@ __device__ __forceinline__ void rmw_force(float* f, int64_t g, double add) {
   f[g] = (float)((double)f[g] + add);
 }
 
+// Completion word of walker w (all threads of the block that finished it, on
+// every exit path): each thread's stores are released at system scope before
+// the barrier, then one store publishes the sequence number.
+__device__ __forceinline__ void signal_done(const ForceArgs& A, int64_t w) {
+  if (!A.done_flag) return;
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(A.done_flag + w, A.done_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Writes the walker's outputs and the optional deposit (thread 0 only).
 template <int D>
 __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, double V) {
@@ -200,10 +233,9 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
     A.dVds[a * A.nw + w] = S.dV[a];
   }
   A.V[w] = V;
-  if (!A.deposit_slot) return;
-  const int64_t slot = A.deposit_slot[w];
+  const int64_t slot = w_deposit_slot(A, w);
   if (slot < 0) return;
-  double hw = A.deposit_height ? A.deposit_height[w] : 1.0;
+  double hw = w_deposit_height(A, w);
   if (slot >= F.H.capacity) {
     atomicOr(A.err, kErrInval);
     return;
@@ -230,8 +262,8 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
 template <int D>
 __device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const Entry (&ent)[kCache]) {
   const int tid = threadIdx.x;
-  const int64_t base = A.atom_base[w];
-  const int64_t mbase = A.mass_base ? A.mass_base[w] : base;
+  const int64_t base = w_atom_base(A, w);
+  const int64_t mbase = w_mass_base(A, w);
   if (S.fast) {
     // Every cached COM/RMSD entry is a distinct atom here (no atom is in two
     // such lists and each list is strictly increasing), so all the old forces
@@ -384,10 +416,10 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
                          Entry (&ent)[kCache], double* red, double (&tpos)[kMaxTors][4][3], int* sh_list) {
   const ForceArgs& A = F.A;
   const int tid = threadIdx.x;
-  const int64_t base = A.atom_base[w];
-  const int64_t mbase = A.mass_base ? A.mass_base[w] : base;
-  const int64_t soff = A.stage_off ? A.stage_off[w] : -1;       // masses staged for this batch
-  const int32_t natoms = A.n_atoms[w];
+  const int64_t base = w_atom_base(A, w);
+  const int64_t mbase = w_mass_base(A, w);
+  const int64_t soff = w_stage_off(A, w);                        // masses staged for this batch
+  const int32_t natoms = w_n_atoms(A, w);
   if (tid == 0) {
     int bad = natoms < 0 ? kErrInval : 0;
     int pos = 0;
@@ -773,7 +805,7 @@ __device__ void finish_common(const FArgs& F, int64_t w, const float (&hi)[D + 1
 enum { kStageCV = 0, kStageGrid = 1, kStageSum = 2 };
 
 template <int D, int STAGE>
-__global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
+__device__ __forceinline__ void cv_stage_body(const FArgs& F) {
   const ForceArgs& A = F.A;
   const int64_t w = blockIdx.x;
   const int tid = threadIdx.x;
@@ -814,11 +846,17 @@ __global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
   }
 }
 
+template <int D, int STAGE>
+__global__ __launch_bounds__(kFBlock) void k_cv_stage(const FArgs F) {
+  cv_stage_body<D, STAGE>(F);
+  if (STAGE != kStageSum) signal_done(F.A, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Fused shape: the whole direct-sum step of one walker in one block.
 // ---------------------------------------------------------------------------
 template <int D, int PMASK, int KERN, bool FP64>
-__global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
+__device__ __forceinline__ void force_fused_body(const FArgs& F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const Consts& K = F.K;
@@ -871,6 +909,12 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
     block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
   }
   finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+}
+
+template <int D, int PMASK, int KERN, bool FP64>
+__global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
+  force_fused_body<D, PMASK, KERN, FP64>(F);
+  signal_done(F.A, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -960,7 +1004,7 @@ __global__ __launch_bounds__(64) void k_sum_parts(const FArgs F) {
 constexpr int kMergeBatch = 16;
 
 template <int D, bool FP64>
-__global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
+__device__ __forceinline__ void finish_stage_body(const FArgs& F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const int64_t w = blockIdx.x;
@@ -1024,6 +1068,12 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
   finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
 }
 
+template <int D, bool FP64>
+__global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
+  finish_stage_body<D, FP64>(F);
+  signal_done(F.A, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Chained shape (few walkers, long history), one launch: block (g, w)
 // computes walker w's CV, the sums of chunks g * kFBlock + t (thread t; each
@@ -1033,8 +1083,9 @@ __global__ __launch_bounds__(kFBlock) void k_finish_stage(const FArgs F) {
 // chain rule), then resets the counter for the next launch. Every block
 // arrives, also for an invalid walker, and no block waits for another.
 // ---------------------------------------------------------------------------
+// Returns whether this block finished the walker (it was the last to arrive).
 template <int D, int PMASK, int KERN, bool FP64>
-__global__ __launch_bounds__(kFBlock) void k_force_chain(const FArgs F) {
+__device__ __forceinline__ bool force_chain_body(const FArgs& F) {
   constexpr int N = D + 1;
   const ForceArgs& A = F.A;
   const Consts& K = F.K;
@@ -1088,7 +1139,8 @@ __global__ __launch_bounds__(kFBlock) void k_force_chain(const FArgs F) {
     if (last) atomicExch(&F.arrived[w], 0u);   // every block of the walker has arrived
   }
   __syncthreads();
-  if (!last || !ok) return;
+  if (!last) return false;
+  if (!ok) return true;
   __threadfence();
   float hi[N], lo[N];
   double v64[N];
@@ -1122,6 +1174,12 @@ __global__ __launch_bounds__(kFBlock) void k_force_chain(const FArgs F) {
   if (FP64) block_sum<N, kFBlock>(v64, red);
   else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
   finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+  return true;
+}
+
+template <int D, int PMASK, int KERN, bool FP64>
+__global__ __launch_bounds__(kFBlock) void k_force_chain(const FArgs F) {
+  if (force_chain_body<D, PMASK, KERN, FP64>(F)) signal_done(F.A, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------

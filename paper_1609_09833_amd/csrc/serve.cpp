@@ -62,8 +62,9 @@ abp_status sfail(abp_status st, const std::string& msg) { return abp::set_error(
 
 constexpr int kMaxLists = 6;
 constexpr int64_t kBytesPerAtom = ABP_SERVER_BYTES_PER_ATOM;
-constexpr size_t kTraceMax = (size_t)1 << 20;  // batch records kept
+constexpr size_t kTraceMax = (size_t)1 << 18;  // batch records kept (a ring, reserved at create)
 constexpr double kSpinSeconds = 2e-3;          // idle time the scheduler spins before it sleeps
+constexpr double kStallCheckSeconds = 2e-3;    // a batch this old also has its stream's state checked
 
 struct Walker {
   int32_t n_atoms = 0;
@@ -101,14 +102,19 @@ struct Slot {
   int64_t version = 0;
   double t_formed = 0.0, t_launched = 0.0;
   int32_t admitted = 0;
-  int64_t commit_seen = 0;           // commits this slot's stream has waited for (GRID)
+  int grid_copy = 0;                 // GRID: the copy of the node arrays the batch reads
   std::vector<int32_t> reqs;         // records
   std::vector<int64_t> dep_slots;    // history slot per request or -1
-  char* h_desc = nullptr;            // pinned descriptor, then the staged masses
-  char* d_desc = nullptr;
+  char* h_desc = nullptr;            // mapped pinned descriptor, then the staged masses
+  char* m_desc = nullptr;            // its device view (read in place by inline batches)
+  char* d_desc = nullptr;            // device copy (larger batches)
   size_t desc_cap = 0;
   double* h_out = nullptr;           // mapped pinned outputs: s[ncv][nb], V[nb], dV[ncv][nb]
   double* m_out = nullptr;           // its device view
+  uint32_t* h_done = nullptr;        // mapped completion words [max_batch]: batch seq when request j is done
+  uint32_t* m_done = nullptr;        // their device view
+  uint32_t seq = 0;                  // this slot's batch counter (0: none launched)
+  bool evented = false;              // `done` recorded after the current batch
   void* d_ws = nullptr;              // bias_force workspace, sized for max_batch at the capacity
 };
 
@@ -163,8 +169,29 @@ struct abp_server {
   std::vector<Slot> slots;
   std::deque<int> launch_order;      // busy slots in launch order
   hipStream_t commit_stream = nullptr;
-  hipEvent_t commit_done = nullptr;  // recorded after every commit (GRID evaluation waits for it)
-  int64_t commit_seq = 0;            // commits issued
+  // GRID evaluation reads one of two copies of the node arrays: [0] is the
+  // context's own (with its FP32 mirror), [1] the server's. A batch reads the
+  // current copy. Committed hills are added to the other copy once no batch
+  // in flight reads it, on the commit stream, and that copy becomes current
+  // when the update has completed (if it is then the newer one): batches never
+  // wait for a commit. Both copies receive the same groups of hills in the
+  // same order, so they are bitwise equal at equal versions.
+  struct GridCopy {
+    double* grid = nullptr;
+    float* grid32 = nullptr;
+    int64_t version = 0;             // hills it holds
+    size_t next = 0;                 // first group (absolute index) not yet added
+  };
+  bool grid_mode = false;
+  GridCopy gcopy[2];
+  int gcur = 0;
+  int gupd = -1;                     // copy being updated, or -1
+  int64_t gupd_version = 0;
+  size_t gupd_next = 0;
+  std::deque<std::pair<int64_t, int64_t>> groups;   // committed hill ranges in commit order
+  size_t gbase = 0;                  // absolute index of groups.front()
+  hipEvent_t grid_evt = nullptr;     // recorded after an update
+  double* own_grid = nullptr;
   std::map<int64_t, bool> dep_done;  // reserved slot -> done
   int64_t resident = 0;
   // request staging: max_pending records, each with a fixed strip of the
@@ -283,15 +310,13 @@ abp_status commit_prefix(abp_server* S) {
   }
   const int64_t before = abp_num_hills(S->ctx);
   if (upto > before) {
-    const bool grid = S->desc.eval_mode == ABP_EVAL_GRID;
-    if (grid)          // batches in flight read the grid of their own version
-      for (const int k : S->launch_order)
-        SRV_TRY(hipStreamWaitEvent(S->commit_stream, S->slots[k].done, 0));
-    const abp_status st = abp_commit(S->ctx, upto, S->commit_stream);
-    if (st != ABP_OK) return st;
-    if (grid) {
-      SRV_TRY(hipEventRecord(S->commit_done, S->commit_stream));
-      S->commit_seq++;
+    if (S->grid_mode) {        // the grid copies take the hills in grid_step
+      const abp_status st = abp::ctx_commit_hills(S->ctx, upto);
+      if (st != ABP_OK) return st;
+      S->groups.emplace_back(before, upto);
+    } else {
+      const abp_status st = abp_commit(S->ctx, upto, S->commit_stream);
+      if (st != ABP_OK) return st;
     }
     std::lock_guard<std::mutex> lk(S->mu_stats);
     S->stats.deposits += upto - before;
@@ -304,22 +329,32 @@ abp_status commit_prefix(abp_server* S) {
 // bias-force launches; deposits: whether deposit steps reserve slots.
 abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int32_t* recs, int64_t nb,
                          int32_t shape, bool deposits) {
-  DescLayout L(nb, S->nlists);
-  int64_t* d_poolo = reinterpret_cast<int64_t*>(sl.h_desc + L.pool_off);
-  int64_t* d_arena = reinterpret_cast<int64_t*>(sl.h_desc + L.arena_off);
-  int64_t* d_stage = reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
-  int64_t* d_dep = reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
-  double* d_hgt = reinterpret_cast<double*>(sl.h_desc + L.dep_height);
-  int32_t* d_ncv = reinterpret_cast<int32_t*>(sl.h_desc + L.n_cv);
-  int32_t* d_lbeg = reinterpret_cast<int32_t*>(sl.h_desc + L.list_beg);
-  int32_t* d_llen = reinterpret_cast<int32_t*>(sl.h_desc + L.list_len);
+  // Up to kInlineWalkers requests: the per-walker fields travel in the kernel
+  // arguments and the staged masses are read from the mapped descriptor
+  // buffer, so nothing is copied before the launch. Larger batches: the
+  // descriptor (fields, then staged masses) is copied to the device first.
+  const bool inl = nb <= abp::kInlineWalkers;
+  abp::ForceArgs A;
+  std::memset(&A, 0, sizeof(A));
+  DescLayout L(inl ? 0 : nb, S->nlists);
+  const int64_t ls = inl ? abp::kInlineWalkers : nb;        // stride of the list arrays
+  int64_t* d_poolo = inl ? A.inl.mass_base : reinterpret_cast<int64_t*>(sl.h_desc + L.pool_off);
+  int64_t* d_arena = inl ? A.inl.atom_base : reinterpret_cast<int64_t*>(sl.h_desc + L.arena_off);
+  int64_t* d_stage = inl ? A.inl.stage_off : reinterpret_cast<int64_t*>(sl.h_desc + L.stage_off);
+  int64_t* d_dep = inl ? A.inl.deposit_slot : reinterpret_cast<int64_t*>(sl.h_desc + L.dep_slot);
+  double* d_hgt = inl ? A.inl.deposit_height : reinterpret_cast<double*>(sl.h_desc + L.dep_height);
+  int32_t* d_ncv = inl ? A.inl.n_atoms : reinterpret_cast<int32_t*>(sl.h_desc + L.n_cv);
+  int32_t* d_lbeg = inl ? &A.inl.list_beg[0][0] : reinterpret_cast<int32_t*>(sl.h_desc + L.list_beg);
+  int32_t* d_llen = inl ? &A.inl.list_len[0][0] : reinterpret_cast<int32_t*>(sl.h_desc + L.list_len);
   float* h_stage = reinterpret_cast<float*>(sl.h_desc + L.total);
   int64_t spos = 0;
   bool any_deposit = false;
   sl.reqs.clear();
   sl.dep_slots.clear();
   sl.admitted = 0;
-  sl.version = abp_num_hills(S->ctx);
+  const bool grid = S->grid_mode;
+  sl.grid_copy = S->gcur;
+  sl.version = grid ? S->gcopy[S->gcur].version : abp_num_hills(S->ctx);
   for (int64_t j = 0; j < nb; ++j) {
     Walker& w = S->walkers[wids[j]];
     const Record& R = S->records[recs[j]];
@@ -339,8 +374,8 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
     }
     int64_t lpos = w.list_base;
     for (int q = 0; q < S->nlists; ++q) {
-      d_lbeg[q * nb + j] = (int32_t)lpos;
-      d_llen[q * nb + j] = w.len[q];
+      d_lbeg[q * ls + j] = (int32_t)lpos;
+      d_llen[q * ls + j] = w.len[q];
       lpos += w.len[q];
     }
     int64_t slot = -1;
@@ -359,27 +394,30 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
     sl.dep_slots.push_back(slot);
   }
   sl.nb = nb;
-  const bool grid = S->desc.eval_mode == ABP_EVAL_GRID;
-  if (grid && sl.commit_seen != S->commit_seq) {     // the grid must hold every hill of the version
-    SRV_TRY(hipStreamWaitEvent(sl.stream, S->commit_done, 0));
-    sl.commit_seen = S->commit_seq;
-  }
-  SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float), hipMemcpyHostToDevice,
-                         sl.stream));
+  const char* desc = inl ? sl.m_desc : sl.d_desc;        // device view of the fields and staged masses
+  if (!inl)
+    SRV_TRY(hipMemcpyAsync(sl.d_desc, sl.h_desc, L.total + (size_t)spos * sizeof(float), hipMemcpyHostToDevice,
+                           sl.stream));
+  else
+    A.inl_n = (int32_t)nb;
   const int64_t M = S->block;
-  abp::ForceArgs A;
-  std::memset(&A, 0, sizeof(A));
   A.ncv = S->ncv;
   for (int a = 0; a < 3; ++a) A.kind[a] = S->kind[a];
-  A.list_beg = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_beg);
-  A.list_len = reinterpret_cast<const int32_t*>(sl.d_desc + L.list_len);
+  if (!inl) {
+    A.list_beg = reinterpret_cast<const int32_t*>(desc + L.list_beg);
+    A.list_len = reinterpret_cast<const int32_t*>(desc + L.list_len);
+    A.atom_base = reinterpret_cast<const int64_t*>(desc + L.arena_off);   // each request's strip
+    A.n_atoms = reinterpret_cast<const int32_t*>(desc + L.n_cv);
+    A.mass_base = reinterpret_cast<const int64_t*>(desc + L.pool_off);
+    A.stage_off = reinterpret_cast<const int64_t*>(desc + L.stage_off);
+    A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(desc + L.dep_slot) : nullptr;
+    A.deposit_height = reinterpret_cast<const double*>(desc + L.dep_height);
+  }
   A.list_idx = S->d_lidx;
   A.ref_x = S->d_rx;
   A.ref_y = S->d_ry;
   A.ref_z = S->d_rz;
   A.nw = nb;
-  A.atom_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.arena_off);   // each request's strip
-  A.n_atoms = reinterpret_cast<const int32_t*>(sl.d_desc + L.n_cv);
   A.x = S->d_arena;
   A.y = S->d_arena + M;
   A.z = S->d_arena + 2 * M;
@@ -387,27 +425,48 @@ abp_status enqueue_batch(abp_server* S, Slot& sl, const int32_t* wids, const int
   A.fy = S->d_arena + 4 * M;
   A.fz = S->d_arena + 5 * M;
   A.mass = S->d_pool;
-  A.mass_base = reinterpret_cast<const int64_t*>(sl.d_desc + L.pool_off);
-  A.stage_off = reinterpret_cast<const int64_t*>(sl.d_desc + L.stage_off);
-  A.stage_mass = reinterpret_cast<const float*>(sl.d_desc + L.total);
+  A.stage_mass = reinterpret_cast<const float*>(desc + L.total);
   A.mass_store = S->d_pool;
   A.force_store = 1;                      // the strips' forces were zeroed at submit
   A.n_visible = nullptr;
   A.n_visible_default = sl.version;
-  A.deposit_slot = any_deposit ? reinterpret_cast<const int64_t*>(sl.d_desc + L.dep_slot) : nullptr;
-  A.deposit_height = reinterpret_cast<const double*>(sl.d_desc + L.dep_height);
   A.s = sl.m_out;
   A.V = sl.m_out + S->ncv * nb;
   A.dVds = sl.m_out + (S->ncv + 1) * nb;
   A.prec = S->desc.prec;
   A.shape = shape;
   A.use_grid = grid ? 1 : 0;
-  A.grid = S->cv.grid;
+  A.grid = grid ? S->gcopy[S->gcur].grid : nullptr;
   A.err = S->cv.err;
+  if (++sl.seq == 0) sl.seq = 1;          // 0 is the words' initial value
+  A.done_flag = sl.m_done;
+  A.done_seq = sl.seq;
   SRV_TRY(abp::launch_bias_force(S->cv.K, S->cv.H, A, sl.d_ws, sl.stream));
-  SRV_TRY(hipEventRecord(sl.done, sl.stream));
+  // A batch with deposits is retired (and its hills committed) only once its
+  // launch has completed on the stream.
+  sl.evented = any_deposit;
+  if (sl.evented) SRV_TRY(hipEventRecord(sl.done, sl.stream));
   sl.busy = true;
   return ABP_OK;
+}
+
+// Whether slot sl's batch is done: every request's completion word holds the
+// batch's seq (and, for a batch with an event, the event has completed, so
+// the commit of its deposits follows the whole launch). hipErrorNotReady
+// while running. A stream that went idle without the words is reported as an
+// error after a grace period (a launch that did not run to its end).
+hipError_t batch_state(abp_server* S, Slot& sl) {
+  for (int64_t j = 0; j < sl.nb; ++j)
+    if (__atomic_load_n(sl.h_done + j, __ATOMIC_ACQUIRE) != sl.seq) {
+      if (now_s(S) - sl.t_launched < kStallCheckSeconds) return hipErrorNotReady;
+      const hipError_t q = hipStreamQuery(sl.stream);
+      if (q == hipErrorNotReady) return hipErrorNotReady;
+      if (q != hipSuccess) return q;
+      for (int64_t i = 0; i < sl.nb; ++i)        // idle: the words must be there now
+        if (__atomic_load_n(sl.h_done + i, __ATOMIC_ACQUIRE) != sl.seq) return hipErrorLaunchFailure;
+      break;
+    }
+  return sl.evented ? hipEventQuery(sl.done) : hipSuccess;
 }
 
 void record_batch(abp_server* S, const Slot& sl, int slot_index, double t_done) {
@@ -425,8 +484,52 @@ void record_batch(abp_server* S, const Slot& sl, int slot_index, double t_done) 
   S->trace_next++;
 }
 
+// GRID: an update in flight, or a copy that lacks committed hills.
+bool grid_work(const abp_server* S) {
+  if (!S->grid_mode) return false;
+  return S->gupd >= 0 || S->gcopy[1 - S->gcur].next < S->gbase + S->groups.size();
+}
+
 bool nothing_to_do(const abp_server* S) {
-  return S->launch_order.empty() && S->ready.empty() && S->admission.empty();
+  return S->launch_order.empty() && S->ready.empty() && S->admission.empty() && !grid_work(S);
+}
+
+// GRID: finishes a completed update of a grid copy (making it current when it
+// is the newer one) and starts the next: the committed groups that the
+// non-current copy lacks, once no batch in flight reads it.
+abp_status grid_step(abp_server* S) {
+  if (!S->grid_mode) return ABP_OK;
+  if (S->gupd >= 0) {
+    const hipError_t q = hipEventQuery(S->grid_evt);
+    if (q == hipErrorNotReady) return ABP_OK;
+    if (q != hipSuccess) return sfail(ABP_E_DEVICE, (std::string("grid update failed: ") + hipGetErrorString(q)).c_str());
+    abp_server::GridCopy& g = S->gcopy[S->gupd];
+    g.version = S->gupd_version;
+    g.next = S->gupd_next;
+    if (g.version > S->gcopy[S->gcur].version) S->gcur = S->gupd;
+    S->gupd = -1;
+    const size_t both = std::min(S->gcopy[0].next, S->gcopy[1].next);
+    while (S->gbase < both) {
+      S->groups.pop_front();
+      S->gbase++;
+    }
+  }
+  const int t = 1 - S->gcur;
+  abp_server::GridCopy& g = S->gcopy[t];
+  const size_t end = S->gbase + S->groups.size();
+  if (g.next >= end) return ABP_OK;
+  for (const int k : S->launch_order)
+    if (S->slots[k].grid_copy == t) return ABP_OK;
+  for (size_t i = g.next; i < end; ++i) {
+    const auto& gr = S->groups[i - S->gbase];
+    const abp_status st = abp::ctx_grid_add(S->ctx, g.grid, g.grid32, gr.first, gr.second, S->commit_stream);
+    if (st != ABP_OK) return st;
+  }
+  SRV_TRY(hipEventRecord(S->grid_evt, S->commit_stream));
+  S->gupd = t;
+  S->gupd_version = S->groups.back().second;
+  S->gupd_next = end;
+  return ABP_OK;
 }
 
 // One scheduler turn's device work (steps 2-4). Returns false on failure
@@ -437,7 +540,7 @@ bool turn(abp_server* S) {
   while (!S->launch_order.empty()) {
     const int idx = S->launch_order.front();
     Slot& sl = S->slots[idx];
-    const hipError_t q = hipEventQuery(sl.done);
+    const hipError_t q = batch_state(S, sl);
     if (q == hipErrorNotReady) break;
     if (q != hipSuccess) {
       S->thread_status = ABP_E_DEVICE;
@@ -476,6 +579,14 @@ bool turn(abp_server* S) {
     sl.busy = false;
     S->launch_order.pop_front();
     const abp_status st = commit_prefix(S);
+    if (st != ABP_OK) {
+      S->thread_status = st;
+      S->thread_error = abp_last_error();
+      return false;
+    }
+  }
+  {
+    const abp_status st = grid_step(S);
     if (st != ABP_OK) {
       S->thread_status = st;
       S->thread_error = abp_last_error();
@@ -586,7 +697,9 @@ abp_status size_buffers(abp_server* S) {
     sl.h_desc = nullptr;
     sl.d_desc = nullptr;
     sl.desc_cap = 0;
-    if (hipHostMalloc((void**)&sl.h_desc, need, hipHostMallocDefault) != hipSuccess ||
+    sl.m_desc = nullptr;
+    if (hipHostMalloc((void**)&sl.h_desc, need, hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&sl.m_desc, sl.h_desc, 0) != hipSuccess ||
         hipMalloc((void**)&sl.d_desc, need) != hipSuccess)
       return sfail(ABP_E_NOMEM, "cannot allocate batch descriptors");
     sl.desc_cap = need;
@@ -709,13 +822,20 @@ abp_status abp_server_create(abp_ctx* ctx, const abp_server_desc* desc, abp_serv
   const int64_t B = desc->max_batch;
   const size_t ws = abp::force_workspace_bytes(B, abp::force_blocks_per_walker(S->cv.H.capacity, 0, 0), S->ncv);
   S->slots.resize(desc->streams);
+  S->trace.reserve(kTraceMax);            // the loop never grows it
+  S->grid_mode = desc->eval_mode == ABP_EVAL_GRID;
   bool good = hipStreamCreateWithFlags(&S->commit_stream, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&S->commit_done, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&S->grid_evt, hipEventDisableTiming) == hipSuccess;
+  if (good && S->grid_mode)
+    good = hipMalloc(&S->own_grid, sizeof(double) * S->cv.grid_doubles) == hipSuccess;
   for (auto& sl : S->slots) {
     good = good && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
            hipHostMalloc((void**)&sl.h_out, sizeof(double) * B * (2 * S->ncv + 1), hipHostMallocMapped) == hipSuccess &&
            hipHostGetDevicePointer((void**)&sl.m_out, sl.h_out, 0) == hipSuccess &&
+           hipHostMalloc((void**)&sl.h_done, sizeof(uint32_t) * B, hipHostMallocMapped) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&sl.m_done, sl.h_done, 0) == hipSuccess &&
+           std::memset(sl.h_done, 0, sizeof(uint32_t) * B) != nullptr &&
            hipMalloc(&sl.d_ws, ws) == hipSuccess && hipMemset(sl.d_ws, 0, ws) == hipSuccess;
     sl.reqs.reserve(B);
     sl.dep_slots.reserve(B);
@@ -739,6 +859,24 @@ abp_status abp_server_stop(abp_server* S) {
     S->stats.wall_seconds = S->t_stop - S->t_start;
   }
   S->running = false;
+  if (S->thread_status == ABP_OK && S->grid_mode) {
+    // the context's own arrays take every group they lack
+    (void)hipSetDevice(S->cv.device);
+    abp_server::GridCopy& g = S->gcopy[0];
+    if (S->gupd >= 0) {
+      if (hipStreamSynchronize(S->commit_stream) != hipSuccess)
+        return sfail(ABP_E_DEVICE, "grid update failed");
+      if (S->gupd == 0) g.next = S->gupd_next;
+      S->gupd = -1;
+    }
+    for (size_t i = g.next; i < S->gbase + S->groups.size(); ++i) {
+      const auto& gr = S->groups[i - S->gbase];
+      const abp_status st = abp::ctx_grid_add(S->ctx, g.grid, g.grid32, gr.first, gr.second, S->commit_stream);
+      if (st != ABP_OK) return st;
+    }
+    g.next = S->gbase + S->groups.size();
+    if (hipStreamSynchronize(S->commit_stream) != hipSuccess) return sfail(ABP_E_DEVICE, "grid update failed");
+  }
   if (S->thread_status != ABP_OK) {
     const abp_status st = S->thread_status;
     S->thread_status = ABP_OK;
@@ -759,13 +897,15 @@ abp_status abp_server_destroy(abp_server* S) {
     if (sl.h_desc) (void)hipHostFree(sl.h_desc);
     if (sl.d_desc) (void)hipFree(sl.d_desc);
     if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.h_done) (void)hipHostFree(sl.h_done);
     if (sl.d_ws) (void)hipFree(sl.d_ws);
   }
   if (S->commit_stream) {
     (void)hipStreamSynchronize(S->commit_stream);
     (void)hipStreamDestroy(S->commit_stream);
   }
-  if (S->commit_done) (void)hipEventDestroy(S->commit_done);
+  if (S->grid_evt) (void)hipEventDestroy(S->grid_evt);
+  if (S->own_grid) (void)hipFree(S->own_grid);
   if (S->arena) (void)hipHostFree(S->arena);
   if (S->d_lidx) (void)hipFree(S->d_lidx);
   if (S->d_rx) (void)hipFree(S->d_rx);
@@ -878,10 +1018,18 @@ abp_status abp_server_start(abp_server* S) {
   for (auto& sl : S->slots) {
     SRV_TRY(hipStreamSynchronize(sl.stream));
     sl.busy = false;
-    sl.commit_seen = 0;
   }
   SRV_TRY(hipStreamSynchronize(S->commit_stream));
-  S->commit_seq = 0;
+  if (S->grid_mode) {        // both copies start from the context's grid
+    SRV_TRY(hipMemcpy(S->own_grid, S->cv.grid, sizeof(double) * S->cv.grid_doubles, hipMemcpyDeviceToDevice));
+    const int64_t v = abp_num_hills(S->ctx);
+    S->gcopy[0] = {S->cv.grid, S->cv.grid32, v, 0};
+    S->gcopy[1] = {S->own_grid, nullptr, v, 0};
+    S->gcur = 0;
+    S->gupd = -1;
+    S->groups.clear();
+    S->gbase = 0;
+  }
   abp_status st = size_buffers(S);
   if (st != ABP_OK) return st;
   st = warm_up(S);

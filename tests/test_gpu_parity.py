@@ -712,6 +712,31 @@ def test_wt_batch_deposit_heights():
     assert want.min() < 0.8 * 0.5                             # the history is dense enough to matter
 
 
+@pytest.mark.parametrize("n_new,f64", [(2 * 16384 + 1000, True), (16384 + 5, False)])
+def test_wt_batch_deposit_across_chunks(n_new, f64):
+    """A well-tempered batch larger than the library's chunk: every new hill's
+    height still sees exactly the history before the call, and the centres
+    (FP64, or FP32 rounded on append) land in order."""
+    import torch
+    device()
+    spec, hills = _wt_spec()
+    ctx = make_ctx(spec, W.Hills(hills.centers, np.ones(hills.n)), capacity=hills.n + n_new)
+    c0, h0 = abp.abp_hills_export(ctx)
+    rng = np.random.default_rng(52)
+    new = rng.uniform(-PI, PI, (2, n_new))
+    dt = torch.float64 if f64 else torch.float32
+    if not f64:
+        new = new.astype(np.float32).astype(np.float64)
+    abp.bias_deposit(ctx, torch.tensor(new, dtype=dt, device="cuda"),
+                     torch.tensor(np.full(n_new, 0.8), dtype=dt, device="cuda"))
+    abp.abp_sync(ctx)
+    c1, h1 = abp.abp_hills_export(ctx)
+    np.testing.assert_array_equal(c1[:, hills.n:], new)
+    want = oracle.wt_heights(spec, c0, h0, new, 0.8 if f64 else float(np.float32(0.8)), 2.5)
+    # FP32 centres: V is returned in FP32 before the exponential
+    np.testing.assert_allclose(h1[hills.n:], want, rtol=1e-12 if f64 else 1e-6)
+
+
 def test_wt_one_deposit_per_step_matches_recurrence():
     device()
     import dataclasses

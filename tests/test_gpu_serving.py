@@ -201,18 +201,26 @@ def test_serving_grid_with_deposits_matches_oracle(lib, drv):
     probe = lib.Server(ctx, wk.kinds)
     ncv = _register(probe, wk)
     probe.close()
-    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=_cv_budget(lib, ncv, 1 / 3), max_batch=16, streams=2,
+    srv = lib.Server(ctx, wk.kinds, hbm_budget_bytes=_cv_budget(lib, ncv, 1 / 3), max_batch=48, streams=2,
                      deposit_every=3, height0=1.2, height_decay=20000.0, eval_mode=lib.ABP_EVAL_GRID)
     _register(srv, wk)
     eng = drv.Engines(srv, wk)
     srv.start()
-    t, w, step = W.serving_requests(seed=7, n_walkers=N_WALKERS, rate=5_000.0, n_requests=300)
+    # bursts: batches both within and above the 16 requests whose fields ride in the kernel arguments
+    t, w, step = W.serving_requests(seed=7, n_walkers=N_WALKERS, rate=60_000.0, n_requests=400)
     out = drv.replay(srv, eng, w, step, t, AMP)
     srv.stop()
     st = srv.stats()
     assert st["completed"] == len(t) and st["evictions"] > 0 and st["deposits"] > 0
+    tr = srv.trace()
+    print(f"batch sizes: max {tr['requests'].max()}, batches above 16: {(tr['requests'] > 16).sum()}")
     dep = out["deposit_slot"]
     assert np.array_equal(dep >= 0, (step % 3) == 0)
+    ver = out["version"]
+    for wi in range(N_WALKERS):                 # a walker never sees an older grid
+        assert np.all(np.diff(ver[w == wi]) >= 0)
+    assert np.unique(ver).size >= 2             # the copies took turns
+    assert ctx.num_hills == 1000 + st["deposits"]
     centers, heights = lib.abp_hills_export(ctx)
     grids = {}
     worst = 0.0
