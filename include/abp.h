@@ -331,11 +331,14 @@ abp_status abp_grid_export(abp_ctx* ctx, double* H_host, int64_t n_values);
  * multiple of deposit_every deposits a hill at its CV value (height
  * height0 * exp(-k / height_decay) for history slot k) into a slot reserved
  * in batch-formation order; slots are committed, in order, once every earlier
- * slot is done. Commits (and their grid deposits) run on one stream; with GRID
- * evaluation a commit waits for the batches in flight and later batches wait
- * for it, so a request reads exactly the grid of the hills of its version. A
- * request's result is bitwise the same whatever batch it runs in. Forces are
- * FP32; s, V and dV/ds FP64. */
+ * slot is done. Commits (and their grid deposits) run on one stream of their
+ * own; with GRID evaluation a request reads a copy of the grid that holds
+ * exactly the hills of its version (see eval_mode), and no batch waits for a
+ * commit. A request's result is bitwise the same whatever batch it runs in.
+ * Forces are FP32; s, V and dV/ds FP64. A batch signals completion through
+ * words in mapped host memory that the scheduler polls; batches of up to 16
+ * requests carry their per-request fields in the kernel arguments, larger ones
+ * in one copied descriptor. */
 typedef struct abp_server abp_server;
 
 #define ABP_SERVER_BYTES_PER_ATOM 4   /* resident device state per CV atom: its FP32 mass */
