@@ -186,9 +186,11 @@ def test_serving_with_deposits_matches_oracle(lib, drv):
 
 
 def test_serving_grid_with_deposits_matches_oracle(lib, drv):
-    """GRID evaluation: batches read the context's grid while the commits of
-    the requests' deposits update it on their own stream; every request must
-    equal the oracle's interpolation of the grid of exactly its version."""
+    """GRID evaluation: batches read one copy of the grid while the commits of
+    the requests' deposits go into the other on their own stream; every
+    request must equal the oracle's interpolation of the grid of exactly its
+    version, the context's grid must hold every hill after stop, and a restart
+    must see hills deposited from outside in between."""
     import dataclasses
     import oracle
     import torch
@@ -236,6 +238,29 @@ def test_serving_grid_with_deposits_matches_oracle(lib, drv):
     H = lib.abp_grid_export(ctx)
     Ho = oracle.grid_all(spec, centers, heights)
     np.testing.assert_allclose(H, Ho, rtol=1e-9, atol=1e-12 * np.abs(Ho).max())
+    # hills from outside between two runs: both copies start from them
+    rng = np.random.default_rng(17)
+    outside = np.stack([rng.uniform(0.2, 1.0, 64), rng.uniform(-np.pi, np.pi, 64)])
+    lib.bias_deposit(ctx, torch.tensor(outside, device="cuda"), torch.tensor(np.full(64, 2.0), device="cuda"))
+    torch.cuda.synchronize()
+    n0 = ctx.num_hills
+    srv.start()
+    t2, w2, step2 = W.serving_requests(seed=8, n_walkers=N_WALKERS, rate=60_000.0, n_requests=200)
+    out2 = drv.replay(srv, eng, w2, step2, t2, AMP)
+    srv.stop()
+    assert np.all(out2["version"] >= n0)
+    centers, heights = lib.abp_hills_export(ctx)
+    grids = {}
+    for r in range(0, len(t2), 5):
+        v = int(out2["version"][r])
+        if v not in grids:
+            grids[v] = oracle.grid_all(spec, centers[:, :v], heights[:v])
+        o, k3 = int(out2["offset"][r]), 3 * int(eng.n_cv[w2[r]])
+        _check_request("grid served after restart", spec, centers, heights, wk, srv, r, int(w2[r]),
+                       out2["positions"][o:o + k3], v, out2["s"][:, r], out2["V"][r], out2["dVds"][:, r],
+                       out2["forces"][o:o + k3], H=grids[v])
+    np.testing.assert_allclose(lib.abp_grid_export(ctx), oracle.grid_all(spec, centers, heights), rtol=1e-9,
+                               atol=1e-12 * np.abs(Ho).max())
     srv.close()
     ctx.close()
 
