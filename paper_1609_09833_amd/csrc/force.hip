@@ -55,6 +55,7 @@ constexpr int kFBlock = 128;
 constexpr int kCache = 6;               // CV-list entries per thread kept in registers
 constexpr int kMaxCached = kCache * kFBlock;
 constexpr int kMaxTors = 3;             // torsion CVs (one per axis at most)
+constexpr int kDupMapAtoms = 32768;     // walkers up to this many atoms: duplicate check by LDS bitmap (4 KiB)
 constexpr double kMinDist = 1e-12;      // below this COM distance the direction is undefined
 constexpr double kMinCross2 = 1e-24;    // collinear torsion atoms
 
@@ -413,21 +414,26 @@ __device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const En
 // applies (no atom in two COM/RMSD lists).
 template <int D>
 __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state, CvState& S,
-                         Entry (&ent)[kCache], double* red, double (&tpos)[kMaxTors][4][3], int* sh_list) {
+                         Entry (&ent)[kCache], double* red, double (&tpos)[kMaxTors][4][3], int* sh_list,
+                         unsigned* dupmap) {
   const ForceArgs& A = F.A;
   const int tid = threadIdx.x;
   const int64_t base = w_atom_base(A, w);
   const int64_t mbase = w_mass_base(A, w);
   const int64_t soff = w_stage_off(A, w);                        // masses staged for this batch
   const int32_t natoms = w_n_atoms(A, w);
+  if (tid < 2 * D) {                       // the lists' bounds, one thread each (loads in parallel)
+    int b, n;
+    list_bounds(A, w, tid, b, n);
+    S.lb[tid] = b;
+    S.ln[tid] = n;
+  }
+  __syncthreads();
   if (tid == 0) {
     int bad = natoms < 0 ? kErrInval : 0;
     int pos = 0;
     for (int q = 0; q < 2 * D; ++q) {
-      int b, n;
-      list_bounds(A, w, q, b, n);
-      S.lb[q] = b;
-      S.ln[q] = n;
+      const int b = S.lb[q], n = S.ln[q];
       S.pos[q] = pos;
       pos += n;
       if (n < 0 || b < 0) bad |= kErrInval;
@@ -456,6 +462,15 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
     return false;
   }
   const int total = S.total;
+  // Atoms in two COM/RMSD lists (which rule out the one-pass chain rule) are
+  // found during the gather through a bitmap of the walker's atoms in LDS,
+  // when the walker is small enough for it; otherwise by binary search after.
+  const bool use_map = !cv_only && S.fast && natoms <= kDupMapAtoms;     // uniform
+  bool dup_seen = false;
+  if (use_map) {
+    for (int i = tid; i < (natoms + 31) / 32; i += kFBlock) dupmap[i] = 0u;
+    __syncthreads();
+  }
 
   // ---- one gather of every entry: validate, accumulate COM / RMSD sums
   // acc: [q*4 + c] mass-weighted x, y, z and mass of list q | [8D + a] RMSD squares | [9D] bad flag
@@ -543,6 +558,10 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
       S.tatom[a][jt] = i;
     }
     if (r < kMaxCached) sh_list[r] = i;
+    if (use_map && kind != ABP_CV_TORSION) {             // i is in [0, natoms) here
+      const unsigned bit = 1u << (i & 31);
+      if (atomicOr(&dupmap[i >> 5], bit) & bit) dup_seen = true;
+    }
     if (soff >= 0) A.mass_store[mbase + i] = m;         // the walker's masses stay on the device
     out.gi = i; out.li = li; out.e = e; out.m = m;
   };
@@ -567,6 +586,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
     consume(r, G, tmp);
   }
   if (badbits) atomicOr(&S.bad, badbits);
+  if (dup_seen) atomicAnd(&S.fast, 0);                   // published by block_sum's barriers
   acc[9 * D] = badbits ? 1.0 : 0.0;
   block_sum<NACC, kFBlock>(acc, red);          // its barriers also publish S.bad, tpos and the torsion atoms
   if (acc[9 * D] != 0.0) {
@@ -667,7 +687,7 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   }
 
   // ---- fast chain-rule path possible? (no atom in two COM/RMSD lists)
-  if (S.fast) {
+  if (S.fast && !use_map) {
     bool dup = false;
 #pragma unroll
     for (int k = 0; k < kCache; ++k) {
@@ -814,7 +834,8 @@ __device__ __forceinline__ void cv_stage_body(const FArgs& F) {
   __shared__ double tpos[kMaxTors][4][3];
   __shared__ int sh_list[kMaxCached];
   Entry ent[kCache];
-  if (!cv_block<D>(F, w, STAGE == kStageCV, STAGE == kStageSum, S, ent, red, tpos, sh_list)) return;
+  __shared__ unsigned dupmap[kDupMapAtoms / 32];
+  if (!cv_block<D>(F, w, STAGE == kStageCV, STAGE == kStageSum, S, ent, red, tpos, sh_list, dupmap)) return;
 
   if (STAGE == kStageSum) {
     const int* src = reinterpret_cast<const int*>(&S);
@@ -867,7 +888,8 @@ __device__ __forceinline__ void force_fused_body(const FArgs& F) {
   __shared__ double tpos[kMaxTors][4][3];
   __shared__ int sh_list[kMaxCached];
   Entry ent[kCache];
-  if (!cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list)) return;
+  __shared__ unsigned dupmap[kDupMapAtoms / 32];
+  if (!cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list, dupmap)) return;
 
   const int64_t nvis = walker_nvis(F, w);
   const int64_t nch = force_chunks(nvis);
@@ -1105,7 +1127,8 @@ __device__ __forceinline__ bool force_chain_body(const FArgs& F) {
   __shared__ int sh_list[kMaxCached];
   __shared__ int last;
   Entry ent[kCache];
-  const bool ok = cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list);   // uniform
+  __shared__ unsigned dupmap[kDupMapAtoms / 32];
+  const bool ok = cv_block<D>(F, w, false, false, S, ent, red, tpos, sh_list, dupmap);   // uniform
   const int64_t nvis = walker_nvis(F, w);
   const int64_t nch = force_chunks(nvis);
   const bool comp = A.prec == ABP_PREC_FP32_KAHAN;
