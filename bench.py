@@ -369,9 +369,8 @@ def serving_leg(abp, W, torch, window_s=1.0):
     res["hist200k_plain_launches_saturated"] = run(srv, eng, "plain saturated", n_win // 10, 131, req_rate=1e12)
     srv.close()
     # GRID evaluation: the same requests read the 256 x 256 grid (kept current
-    # by the deposits' commits) instead of summing the 200k hills; three
-    # batches in flight (p99 65-77 us against 74-88 with two, 83-88 with four)
-    srv, eng = server(budget, 1024, 3, abp.ABP_EVAL_GRID)
+    # by the deposits' commits) instead of summing the 200k hills
+    srv, eng = server(budget, 1024, 2, abp.ABP_EVAL_GRID)
     run(srv, eng, "grid warm-up (not reported)", n_win // 5, 139)
     res["hist200k_budget2MiB_grid"] = run(srv, eng, "200k hills, 2 MiB, grid", n_win, 140)
     res["hist200k_budget2MiB_grid_saturated"] = run(srv, eng, "grid saturated", n_win, 141, req_rate=1e12)
