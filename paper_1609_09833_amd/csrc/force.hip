@@ -211,6 +211,37 @@ __device__ __forceinline__ void block_merge_f32(float (&h)[N], float (&l)[N], bo
   __syncthreads();
 }
 
+// block_sum restricted to the entries whose bit is set in `mask` (uniform
+// across the block): the same fixed order (wave butterfly, then waves in
+// order) for those, the others left as they are.
+template <int N>
+__device__ __forceinline__ void block_sum_masked(double (&v)[N], double* red, uint32_t mask) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    if (!((mask >> r) & 1u)) continue;
+    double x = v[r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[r] = x;
+  }
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+      if ((mask >> r) & 1u) red[wave * N + r] = v[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    if (!((mask >> r) & 1u)) continue;
+    double t = 0.0;
+    for (int w = 0; w < kFBlock / 64; ++w) t += red[w * N + r];
+    v[r] = t;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void rmw_force(float* f, int64_t g, double add) {
   f[g] = (float)((double)f[g] + add);
 }
@@ -588,7 +619,15 @@ __device__ bool cv_block(const FArgs& F, int64_t w, bool cv_only, bool to_state,
   if (badbits) atomicOr(&S.bad, badbits);
   if (dup_seen) atomicAnd(&S.fast, 0);                   // published by block_sum's barriers
   acc[9 * D] = badbits ? 1.0 : 0.0;
-  block_sum<NACC, kFBlock>(acc, red);          // its barriers also publish S.bad, tpos and the torsion atoms
+  // only the sums the CV kinds read: a COM list's four, an RMSD list's
+  // squares, and the flag
+  uint32_t mask = 1u << (9 * D);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (S.kind[a] == ABP_CV_COM_DIST) mask |= 0xFFu << (8 * a);
+    if (S.kind[a] == ABP_CV_RMSD_OFF) mask |= 1u << (8 * D + a);
+  }
+  block_sum_masked<NACC>(acc, red, mask);      // its barriers also publish S.bad, tpos and the torsion atoms
   if (acc[9 * D] != 0.0) {
     if (tid == 0) {
       atomicOr(A.err, S.bad ? S.bad : kErrIndex);
