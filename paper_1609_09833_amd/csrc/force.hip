@@ -290,9 +290,19 @@ __device__ void write_outputs(const FArgs& F, int64_t w, const CvState& S, doubl
   F.H.rec32[slot] = rec;
 }
 
+// Old forces of a thread's cached entries, read ahead of the chain rule (the
+// finish launch issues them before it merges its chunk sums, so their
+// latency overlaps the merge): pre[k] for entry k with an atom, when
+// `valid`; otherwise apply_forces reads them itself.
+struct OldForces {
+  float f[kCache][3];
+  bool valid;
+};
+
 // Chain rule for one walker (all threads of the block; S.dV set).
 template <int D>
-__device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const Entry (&ent)[kCache]) {
+__device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const Entry (&ent)[kCache],
+                             const OldForces& pre) {
   const int tid = threadIdx.x;
   const int64_t base = w_atom_base(A, w);
   const int64_t mbase = w_mass_base(A, w);
@@ -300,21 +310,36 @@ __device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const En
     // Every cached COM/RMSD entry is a distinct atom here (no atom is in two
     // such lists and each list is strictly increasing), so all the old forces
     // can be read before any is written back: one round trip per thread
-    // instead of one per entry.
+    // instead of one per entry, issued before the additions are formed.
     double add[kCache][3];
     int64_t gat[kCache];
     bool live[kCache];
+    float old[kCache][3];
 #pragma unroll
     for (int k = 0; k < kCache; ++k) {
       const Entry en = ent[k];
-      live[k] = false;
-      gat[k] = 0;
+      live[k] = en.gi >= 0 && S.kind[en.li >> 1] != ABP_CV_TORSION;
+      gat[k] = base + (en.gi >= 0 ? en.gi : 0);
+      old[k][0] = old[k][1] = old[k][2] = 0.0f;
+      if (!live[k] || A.force_store) continue;
+      if (pre.valid) {
+        old[k][0] = pre.f[k][0];
+        old[k][1] = pre.f[k][1];
+        old[k][2] = pre.f[k][2];
+      } else {
+        old[k][0] = A.fx[gat[k]];
+        old[k][1] = A.fy[gat[k]];
+        old[k][2] = A.fz[gat[k]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) {
+      const Entry en = ent[k];
       add[k][0] = add[k][1] = add[k][2] = 0.0;
-      if (en.gi < 0) continue;
+      if (!live[k]) continue;
       const int a = en.li >> 1, t = en.li & 1;
       const int kind = S.kind[a];
-      if (kind == ABP_CV_TORSION) continue;
-      const int64_t gi = base + en.gi;
+      const int64_t gi = gat[k];
       const double ga = S.dV[a];
       double fx, fy, fz;
       if (kind == ABP_CV_COM_DIST) {
@@ -341,20 +366,9 @@ __device__ void apply_forces(const ForceArgs& A, int64_t w, CvState& S, const En
             S.tclaimed[b2][j] = 1;
           }
       }
-      live[k] = true;
-      gat[k] = gi;
       add[k][0] = fx;
       add[k][1] = fy;
       add[k][2] = fz;
-    }
-    float old[kCache][3];
-#pragma unroll
-    for (int k = 0; k < kCache; ++k) {
-      old[k][0] = old[k][1] = old[k][2] = 0.0f;
-      if (!live[k] || A.force_store) continue;
-      old[k][0] = A.fx[gat[k]];
-      old[k][1] = A.fy[gat[k]];
-      old[k][2] = A.fz[gat[k]];
     }
 #pragma unroll
     for (int k = 0; k < kCache; ++k) {
@@ -836,7 +850,8 @@ __device__ __forceinline__ void merge_part(float (&hi)[N], float (&lo)[N], doubl
 // and ent hold the walker's CV state and cached entries).
 template <int D, bool FP64>
 __device__ void finish_common(const FArgs& F, int64_t w, const float (&hi)[D + 1], const float (&lo)[D + 1],
-                              const double (&v64)[D + 1], CvState& S, const Entry (&ent)[kCache]) {
+                              const double (&v64)[D + 1], CvState& S, const Entry (&ent)[kCache],
+                              const OldForces& pre) {
   constexpr int N = D + 1;
   const Consts& K = F.K;
   double tot[N];
@@ -853,7 +868,7 @@ __device__ void finish_common(const FArgs& F, int64_t w, const float (&hi)[D + 1
     write_outputs<D>(F, w, S, V);
   }
   __syncthreads();
-  apply_forces<D>(F.A, w, S, ent);
+  apply_forces<D>(F.A, w, S, ent, pre);
 }
 
 // ---------------------------------------------------------------------------
@@ -902,7 +917,9 @@ __device__ __forceinline__ void cv_stage_body(const FArgs& F) {
       write_outputs<D>(F, w, S, V);
     }
     __syncthreads();
-    apply_forces<D>(A, w, S, ent);
+    OldForces none;
+    none.valid = false;
+    apply_forces<D>(A, w, S, ent, none);
   }
 }
 
@@ -969,7 +986,9 @@ __device__ __forceinline__ void force_fused_body(const FArgs& F) {
     }
     block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
   }
-  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+  OldForces none;
+  none.valid = false;
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent, none);
 }
 
 template <int D, int PMASK, int KERN, bool FP64>
@@ -1105,6 +1124,24 @@ __device__ __forceinline__ void finish_stage_body(const FArgs& F) {
     ent[k].m = 0.0f;
     if (k * kFBlock + tid < total) ent[k] = in[k * kFBlock + tid];
   }
+  // the old forces of the cached entries (the one-pass chain rule's reads),
+  // in flight while the chunk sums are merged; entries of a torsion list are
+  // read too and ignored
+  OldForces pre;
+  pre.valid = !A.force_store && total <= kMaxCached;
+  {
+    const int64_t fbase = w_atom_base(A, w);
+#pragma unroll
+    for (int k = 0; k < kCache; ++k) {
+      pre.f[k][0] = pre.f[k][1] = pre.f[k][2] = 0.0f;
+      if (pre.valid && ent[k].gi >= 0) {
+        const int64_t g = fbase + ent[k].gi;
+        pre.f[k][0] = A.fx[g];
+        pre.f[k][1] = A.fy[g];
+        pre.f[k][2] = A.fz[g];
+      }
+    }
+  }
   // kMergeBatch of a thread's chunk sums are loaded before any is merged (the
   // loads overlap; the merge order is unchanged)
   for (int64_t c0 = tid; c0 < nch; c0 += kMergeBatch * kFBlock) {
@@ -1134,7 +1171,7 @@ __device__ __forceinline__ void finish_stage_body(const FArgs& F) {
   }
   if (FP64) block_sum<N, kFBlock>(v64, red);
   else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
-  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent, pre);
 }
 
 template <int D, bool FP64>
@@ -1243,7 +1280,9 @@ __device__ __forceinline__ bool force_chain_body(const FArgs& F) {
   }
   if (FP64) block_sum<N, kFBlock>(v64, red);
   else block_merge_f32<N>(hi, lo, comp, reinterpret_cast<float*>(red));
-  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent);
+  OldForces none;
+  none.valid = false;
+  finish_common<D, FP64>(F, w, hi, lo, v64, S, ent, none);
   return true;
 }
 
