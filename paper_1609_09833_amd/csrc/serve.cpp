@@ -9,26 +9,32 @@
 // Threads. Callers submit and poll from any host threads. A scheduler thread,
 // started by abp_server_start, owns every device call. Each turn it
 //   1. takes newly submitted requests into per-walker FIFOs,
-//   2. retires finished batches (event polled): records results, hands them
-//      to the poll queue, frees the walkers for their next request, and
-//      commits history slots, in order, on one commit stream once every
-//      earlier slot is done (so grid deposits never overlap),
-//   3. admits waiting walkers first come first served into the device pool,
+//   2. retires finished batches (their completion words in mapped host
+//      memory polled, plus the event of a batch with deposits): records
+//      results, hands them to the poll queue, frees the walkers for their
+//      next request, and commits history slots, in order, once every earlier
+//      slot is done,
+//   3. (GRID) finishes a completed update of the non-current grid copy and
+//      starts the next, on the commit stream (so grid deposits never overlap),
+//   4. admits waiting walkers first come first served into the device pool,
 //      evicting least recently used idle walkers when the budget is short,
-//   4. if a batch slot is free, forms a batch from the walkers that are
+//   5. if a batch slot is free, forms a batch from the walkers that are
 //      resident, idle and have a request, and enqueues on the slot's stream
-//      the descriptor upload (with the masses of walkers admitted for it),
-//      the bias-force launches and an event.
+//      the bias-force launches (preceded by a descriptor upload for batches
+//      above kInlineWalkers requests; smaller ones carry their per-request
+//      fields in the kernel arguments).
 // Positions and forces never pass through device copies: the bias-force
 // kernels read each request's CV-atom positions from its pinned, mapped
 // host staging and write the forces there (posted writes, no read-back), and
 // write s, V and dV/ds straight into mapped host memory. A walker's resident
 // device state is its CV-atom masses (the pool the budget bounds); a walker
-// admitted for a batch gets its masses in the batch descriptor, and the CV
-// stage stores them into its pool range for later batches.
-// Requests in one batch see the same history version (hills committed when
-// the batch was formed); deposits go to slots reserved in formation order.
-// Every buffer is sized at start: the loop itself allocates nothing.
+// admitted for a batch gets its masses staged in the slot's mapped
+// descriptor buffer, and the CV stage stores them into its pool range for
+// later batches.
+// Requests in one batch see the same history version (DIRECT: the hills
+// committed when the batch was formed; GRID: the hills of the grid copy it
+// reads); deposits go to slots reserved in formation order.
+// Every buffer is sized at create or start: the loop itself allocates nothing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
