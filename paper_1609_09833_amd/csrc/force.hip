@@ -16,7 +16,7 @@
 // consecutive hills, each summed in increasing order (FP32 terms folded into
 // a Kahan sum every 32 terms, or FP64); thread t of a 128-thread block merges
 // chunks t, t + 128, ... in that order (error-free FP32 TwoSum steps, or FP64
-// adds), then a fixed block tree merges the threads. Two launch shapes
+// adds), then a fixed block tree merges the threads. Three launch shapes
 // compute exactly this:
 //   fused (a short history): one launch, the walker's block does the CV
 //     part, sums its own chunks and finishes;
@@ -24,7 +24,10 @@
 //     (chunk, 64 walkers) that stages the chunk's 64 hill records in LDS (one
 //     coalesced load per lane, so each record is fetched once per 64 walkers)
 //     and in which every lane sums the chunk at its walker's CV value from
-//     LDS broadcasts, and a finish launch that merges the chunk sums.
+//     LDS broadcasts, and a finish launch that merges the chunk sums;
+//   chained (a long history, one or two walkers): one launch of several
+//     blocks per walker, each computing the CV and summing 128 chunks, the
+//     last to arrive (per-walker counter) merging and finishing.
 // So a walker's result is bitwise the same alone or in any batch, whichever
 // shape runs. No block waits for another; no atomics touch sums or forces.
 //
@@ -48,9 +51,9 @@
 namespace abp {
 namespace {
 
-// Threads per walker block. Two waves: at the CV part's register footprint
-// (about 150 VGPRs, 3 waves per SIMD) a CU holds 6 walker blocks, so 1,024
-// walkers are resident at once.
+// Threads per walker block. Two waves: at the walker kernels' register
+// footprint (150-185 VGPRs, 2-3 waves per SIMD) a CU holds 4-6 walker
+// blocks, so 1,024 walkers are resident at once.
 constexpr int kFBlock = 128;
 constexpr int kCache = 6;               // CV-list entries per thread kept in registers
 constexpr int kMaxCached = kCache * kFBlock;
