@@ -35,6 +35,8 @@ struct abp_ctx {
   void* fws = nullptr;                // bias_force: CV state, atom lists, partial sums
   size_t fws_bytes = 0;
   void* wt_buf = nullptr;             // bias_deposit (well-tempered): kWtChunk centres, their V and dV/ds
+  uint32_t* dirty = nullptr;          // deposit tiles reached, by epoch (VALU-deposited 2-D / 3-D grids)
+  uint32_t epoch = 0;
   int32_t force_shape = ABP_SHAPE_AUTO;
 
   HistView hist() const {
@@ -270,8 +272,12 @@ abp_status grid_add_to(abp_ctx* ctx, double* grid, float* grid32, int64_t k0, in
   const size_t need = abp::grid_deposit_scratch_bytes(ctx->K, k1 - k0);
   abp_status st = grow_scratch(ctx, need);
   if (st != ABP_OK) return st;
-  HIP_TRY(abp::launch_grid_deposit(ctx->K, ctx->hist(), k0, k1, grid, need ? ctx->scratch : nullptr, stream));
-  if (grid32) HIP_TRY(abp::launch_grid_mirror(ctx->K, grid, grid32, stream));
+  // tiles the deposit reaches are marked with a fresh epoch; the mirror
+  // refresh then rewrites only their entries (compact hills on the VALU deposit)
+  if (++ctx->epoch == 0) ctx->epoch = 1;
+  HIP_TRY(abp::launch_grid_deposit(ctx->K, ctx->hist(), k0, k1, grid, need ? ctx->scratch : nullptr, ctx->dirty,
+                                   ctx->epoch, stream));
+  if (grid32) HIP_TRY(abp::launch_grid_mirror(ctx->K, grid, grid32, ctx->dirty, ctx->epoch, stream));
   return ABP_OK;
 }
 
@@ -291,6 +297,7 @@ void free_all(abp_ctx* ctx) {
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->fws) (void)hipFree(ctx->fws);
   if (ctx->wt_buf) (void)hipFree(ctx->wt_buf);
+  if (ctx->dirty) (void)hipFree(ctx->dirty);
 }
 
 }  // namespace
@@ -327,6 +334,10 @@ abp_status abp_create(const abp_bias_desc* desc, int device, abp_ctx** out) {
   if (good && ctx->K.nodes > 0)
     good = hipMalloc(&ctx->grid, sizeof(double) * (size_t)(ctx->K.nodes << desc->ndim)) == hipSuccess &&
            hipMalloc(&ctx->grid32, sizeof(float) * abp::grid_mirror_floats(ctx->K)) == hipSuccess;
+  const size_t ntiles = abp::grid_dirty_tiles(ctx->K);
+  if (good && ntiles)
+    good = hipMalloc(&ctx->dirty, sizeof(uint32_t) * ntiles) == hipSuccess &&
+           hipMemset(ctx->dirty, 0, sizeof(uint32_t) * ntiles) == hipSuccess;
   if (good) {
     good = hipMemset(ctx->err, 0, sizeof(int32_t)) == hipSuccess &&
            hipMemset(ctx->clamped, 0, sizeof(unsigned long long)) == hipSuccess &&

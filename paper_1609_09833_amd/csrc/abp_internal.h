@@ -87,9 +87,15 @@ hipError_t launch_direct_sum(const Consts& K, const HistView& H, int64_t n_visib
 
 // Grid accumulation of hills [k0, k1) into the FP64 node arrays. `scratch`
 // must hold scratch_bytes_for(...) bytes (may be NULL when that is 0).
+// Grids deposited tile by tile on the VALU (compact hills, 2-D and 3-D) can
+// record which tiles a deposit reached: `dirty` (grid_dirty_tiles entries, or
+// NULL) gets `epoch` for each such tile, so that the mirror refresh of the
+// same epoch skips the others.
 size_t grid_deposit_scratch_bytes(const Consts& K, int64_t nhills);
+size_t grid_dirty_tiles(const Consts& K);
 hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, int64_t k1,
-                               double* grid, double* scratch, hipStream_t stream);
+                               double* grid, double* scratch, uint32_t* dirty, uint32_t epoch,
+                               hipStream_t stream);
 
 // grid32 (optional): the FP32 mirror of grid; when given the interpolation
 // reads it instead (FP64 arithmetic either way).
@@ -99,7 +105,10 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, const float* gr
 // Refreshes the FP32 mirror grid32 of the node arrays grid (cell-major for
 // 1-D and 2-D grids, node-major for 3-D; grid_mirror_floats entries).
 size_t grid_mirror_floats(const Consts& K);
-hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, hipStream_t stream);
+// With `dirty` (see launch_grid_deposit), only entries whose source node lies
+// in a tile marked `epoch` are refreshed.
+hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, const uint32_t* dirty,
+                              uint32_t epoch, hipStream_t stream);
 
 // The per-walker fields of a batch of up to kInlineWalkers walkers, carried
 // in the kernel arguments (the serving loop's small batches), so that no copy

@@ -50,6 +50,8 @@ struct DepositArgs {
   int64_t tiles;           // node tiles
   double* grid;
   double* scratch;         // [nsplit][nodes][2^D] when nsplit > 1
+  uint32_t* dirty;         // [tiles] or NULL: `epoch` for every tile a hill reached
+  uint32_t epoch;
 };
 
 constexpr double kHalfLog2e = 0.72134752044448170368;   // log2(e) / 2
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
 #pragma unroll
       for (int m = 0; m < NM; ++m) acc[c][r][m] = 0.0;
 
+  bool touched = false;                       // some hill reaches the tile (uniform)
   for (int64_t kc = kb; kc < ke; kc += kKC) {
     const int nk = (int)(ke - kc < kKC ? ke - kc : kKC);
     __syncthreads();
@@ -190,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
     __syncthreads();
     for (int k = 0; k < nk; ++k) {
       if (!(live_x[k] && live_y[k])) continue;     // uniform across the block
+      touched = true;
       double2 xf[COLS];
 #pragma unroll
       for (int c = 0; c < COLS; ++c) xf[c] = Xf[k][lane + 64 * c];
@@ -213,6 +217,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit_nd(const DepositArgs A) {
       }
     }
   }
+  if (touched && A.dirty && threadIdx.x == 0) A.dirty[tile] = A.epoch;
+  // a tile no hill reaches keeps its nodes as they are (the split's partial
+  // grids still get their zeros)
+  if (!touched && A.nsplit == 1) return;
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
     const int64_t xj = x0 + lane + 64 * c;
@@ -590,8 +598,14 @@ size_t grid_deposit_scratch_bytes(const Consts& K, int64_t nhills) {
   return (size_t)s * (size_t)K.nodes * ((size_t)1 << K.ndim) * sizeof(double);
 }
 
+size_t grid_dirty_tiles(const Consts& K) {
+  if (K.nodes <= 0 || K.ndim < 2 || uses_mfma(K)) return 0;
+  return (size_t)node_tiles(K);
+}
+
 hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, int64_t k1,
-                               double* grid, double* scratch, hipStream_t stream) {
+                               double* grid, double* scratch, uint32_t* dirty, uint32_t epoch,
+                               hipStream_t stream) {
   if (k1 <= k0) return hipSuccess;
   DepositArgs A;
   A.K = K;
@@ -605,6 +619,8 @@ hipError_t launch_grid_deposit(const Consts& K, const HistView& H, int64_t k0, i
   A.tiles = node_tiles(K);
   A.grid = grid;
   A.scratch = scratch;
+  A.dirty = grid_dirty_tiles(K) ? dirty : nullptr;
+  A.epoch = epoch;
   const unsigned blocks = (unsigned)(A.tiles * A.nsplit);
   switch (K.ndim) {
     case 1: hipLaunchKernelGGL(k_deposit_1d, dim3(blocks), dim3(kBlock), 0, stream, A); break;
@@ -675,10 +691,24 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, const float* gr
 
 namespace {
 // Node-major mirror (3-D): entry for entry.
-__global__ __launch_bounds__(kBlock) void k_grid_mirror_nodes(const double* __restrict__ grid,
-                                                               float* __restrict__ g32, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+// A node's tile in the VALU deposit's tiling (64 x 32 nodes, one z plane).
+__device__ __forceinline__ int64_t deposit_tile(const Consts& K, int64_t j0, int64_t j1, int64_t j2) {
+  constexpr int TX = 64 * kCols, TY = 4 * kRY;
+  const int64_t tiles_x = (K.grid_n[0] + TX - 1) / TX, tiles_y = (K.grid_n[1] + TY - 1) / TY;
+  return j0 / TX + tiles_x * (j1 / TY + tiles_y * j2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_mirror_nodes(const Consts K, const double* __restrict__ grid,
+                                                               float* __restrict__ g32, int64_t n,
+                                                               const uint32_t* __restrict__ dirty, uint32_t epoch) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    if (dirty) {
+      const int64_t node = i >> 3;                   // 8 entries per 3-D node
+      const int64_t n0 = K.grid_n[0], n1 = K.grid_n[1];
+      if (dirty[deposit_tile(K, node % n0, (node / n0) % n1, node / (n0 * n1))] != epoch) continue;
+    }
     g32[i] = (float)grid[i];
+  }
 }
 
 // Cell-major mirror (1-D, 2-D): one thread per (cell, corner) writes that
@@ -686,7 +716,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_mirror_nodes(const double* __re
 // the last node (never read).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_grid_mirror_cells(const Consts K, const double* __restrict__ grid,
-                                                               float* __restrict__ g32) {
+                                                               float* __restrict__ g32,
+                                                               const uint32_t* __restrict__ dirty, uint32_t epoch) {
   constexpr int NM = 1 << D;
   const int64_t n0 = K.grid_n[0], n1 = D > 1 ? K.grid_n[1] : 1;
   const int64_t total = n0 * n1 * NM;
@@ -702,6 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_mirror_cells(const Consts K, co
         if (j[a] == n[a]) j[a] = K.periodic[a] ? 0 : n[a] - 1;
       }
     }
+    if (D > 1 && dirty && dirty[deposit_tile(K, j[0], j[1], 0)] != epoch) continue;   // source node unchanged
     const double* src = grid + (j[0] + (D > 1 ? j[1] * n0 : 0)) * NM;
     float* dst = g32 + i * NM;
 #pragma unroll
@@ -716,13 +748,17 @@ size_t grid_mirror_floats(const Consts& K) {
   return K.ndim <= 2 ? (size_t)K.nodes * nm * nm : (size_t)K.nodes * nm;
 }
 
-hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, hipStream_t stream) {
+hipError_t launch_grid_mirror(const Consts& K, const double* grid, float* grid32, const uint32_t* dirty,
+                              uint32_t epoch, hipStream_t stream) {
   if (K.nodes <= 0) return hipSuccess;
+  if (!grid_dirty_tiles(K)) dirty = nullptr;           // matrix-core deposits reach every tile
   const int64_t n = (int64_t)grid_mirror_floats(K) / (K.ndim <= 2 ? (1 << K.ndim) : 1);
   const unsigned blocks = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
-  if (K.ndim == 1) hipLaunchKernelGGL(k_grid_mirror_cells<1>, dim3(blocks), dim3(kBlock), 0, stream, K, grid, grid32);
-  else if (K.ndim == 2) hipLaunchKernelGGL(k_grid_mirror_cells<2>, dim3(blocks), dim3(kBlock), 0, stream, K, grid, grid32);
-  else hipLaunchKernelGGL(k_grid_mirror_nodes, dim3(blocks), dim3(kBlock), 0, stream, grid, grid32, n);
+  if (K.ndim == 1)
+    hipLaunchKernelGGL(k_grid_mirror_cells<1>, dim3(blocks), dim3(kBlock), 0, stream, K, grid, grid32, nullptr, 0u);
+  else if (K.ndim == 2)
+    hipLaunchKernelGGL(k_grid_mirror_cells<2>, dim3(blocks), dim3(kBlock), 0, stream, K, grid, grid32, dirty, epoch);
+  else hipLaunchKernelGGL(k_grid_mirror_nodes, dim3(blocks), dim3(kBlock), 0, stream, K, grid, grid32, n, dirty, epoch);
   return hipGetLastError();
 }
 

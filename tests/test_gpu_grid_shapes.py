@@ -146,3 +146,33 @@ def test_quantised_direct_sum_offset_grid(ndim, kernel):
     Vq, dVq, _ = oracle.transform(spec, hq, dhq)
     check_bound("quantised look-up V", Vg.cpu().numpy(), Vq, sV, 1e-9)
     check_bound("quantised look-up dV", dVg.cpu().numpy(), dVq, sG, 1e-9)
+
+
+@pytest.mark.parametrize("ndim,grid_n,quantize", [(2, (150, 100), 0), (2, (150, 100), 1), (3, (70, 40, 6), 0)])
+def test_compact_deposits_refresh_the_mirror_where_they_land(ndim, grid_n, quantize):
+    """Compact hills deposited one at a time (the VALU deposit marks the tiles
+    it reaches, and the FP32 mirror is refreshed only there): after every
+    deposit, FP32-mode evaluations (which read the mirror) must agree with
+    FP64-mode evaluations (which read the node arrays) everywhere, and the
+    node arrays with the oracle's grid."""
+    import dataclasses
+    from paper_1609_09833_amd import abp
+    device()
+    periodic = (1,) + (0,) * (ndim - 1)
+    spec = dataclasses.replace(_spec(ndim, periodic, grid_n, kernel=W.KERNEL_COMPACT), quantize=quantize)
+    hills = _hills(spec, 12, 91 + ndim)
+    ctx = abp.Context(spec, capacity=hills.n)
+    rng = np.random.default_rng(7)
+    q = np.vstack([rng.uniform(spec.lo[i], spec.hi[i], 8192) for i in range(ndim)])
+    qd = to_dev(q)
+    for k in range(hills.n):
+        abp.bias_deposit(ctx, to_dev(hills.centers[:, k:k + 1]), to_dev(hills.heights[k:k + 1]))
+        V64, dV64 = abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP64)
+        V32, dV32 = abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP32_KAHAN)
+        abp.abp_sync(ctx)
+        V64, dV64, V32, dV32 = (t.cpu().numpy() for t in (V64, dV64, V32, dV32))
+        scale = max(np.abs(V64).max(), 1e-30)
+        assert np.abs(V32 - V64).max() <= 1e-5 * scale, (k, np.abs(V32 - V64).max(), scale)
+        gscale = max(np.abs(dV64).max(), 1e-30)
+        assert np.abs(dV32 - dV64).max() <= 1e-4 * gscale, (k, np.abs(dV32 - dV64).max(), gscale)
+    _check(spec, abp.abp_grid_export(ctx), hills)
