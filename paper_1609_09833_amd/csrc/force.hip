@@ -1010,7 +1010,7 @@ __global__ __launch_bounds__(kFBlock) void k_force_fused(const FArgs F) {
 constexpr int kChunksPerWave = 1;   // consecutive chunks one wave sums
 // Waves per block of the sum launch, each with its own chunks of the same 64
 // walkers (1,024 walkers, 20,000 hills: 1 -> 14.7 us, 2 -> 14.4, 4 -> 13.4,
-// 8 -> 14.3).
+// 8 -> 14.3; two or four chunks per wave were slower at every block size).
 constexpr int kSumWaves = 4;
 
 template <int D, int PMASK, int KERN, bool FP64>
