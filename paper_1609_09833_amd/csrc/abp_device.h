@@ -225,6 +225,99 @@ __device__ __forceinline__ void apply_transform(const Consts& K, double h, const
 // Returns h and the analytic gradient; *clamped is set when a non-periodic
 // coordinate lay outside [lo, hi].
 // ---------------------------------------------------------------------------
+// Per axis: the cell (lower node j0, upper j1) and the basis along it, for
+// [cell end][datum: value/derivative].
+template <int D> struct HermCell {
+  int64_t j0[D], j1[D];
+  double A[D][2][2], B[D][2][2];   // interpolant and its derivative d/ds_i
+};
+
+template <int D>
+__device__ __forceinline__ void hermite_locate(const Consts& K, const double (&s)[D], HermCell<D>& C,
+                                               bool& clamped) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int64_t n = K.grid_n[i];
+    const double dx = K.grid_dx[i];
+    double x = s[i], t;
+    if (K.periodic[i]) {
+      // wrap into one period first, so any finite coordinate lands in a cell
+      double f = (x - K.lo[i]) * K.inv_period[i];
+      f -= floor(f);
+      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
+      const double u = f * (double)n;
+      int64_t j = (int64_t)u;
+      j = j > n - 1 ? n - 1 : j;
+      t = u - (double)j;
+      C.j0[i] = j;
+      C.j1[i] = (j + 1 == n) ? 0 : j + 1;
+    } else {
+      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
+      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
+      const double u = (x - K.lo[i]) / dx;
+      int64_t j = (int64_t)u;
+      j = j > n - 2 ? n - 2 : j;
+      j = j < 0 ? 0 : j;
+      t = u - (double)j;
+      C.j0[i] = j;
+      C.j1[i] = j + 1;
+    }
+    const double t2 = t * t, t3 = t2 * t;
+    // values of h00, h10 (times dx), h01, h11 (times dx) and their d/ds
+    C.A[i][0][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
+    C.A[i][0][1] = (t3 - 2.0 * t2 + t) * dx;
+    C.A[i][1][0] = -2.0 * t3 + 3.0 * t2;
+    C.A[i][1][1] = (t3 - t2) * dx;
+    C.B[i][0][0] = (6.0 * t2 - 6.0 * t) / dx;
+    C.B[i][0][1] = 3.0 * t2 - 4.0 * t + 1.0;
+    C.B[i][1][0] = (-6.0 * t2 + 6.0 * t) / dx;
+    C.B[i][1][1] = 3.0 * t2 - 2.0 * t;
+  }
+}
+
+// The node of a cell corner (bit i: upper end along axis i).
+template <int D>
+__device__ __forceinline__ int64_t hermite_node(const Consts& K, const HermCell<D>& C, int corner) {
+  int64_t node = 0, stride = 1;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    node += (((corner >> i) & 1) ? C.j1[i] : C.j0[i]) * stride;
+    stride *= K.grid_n[i];
+  }
+  return node;
+}
+
+// Sum over the corners' node values Hc[corner][entry] with the tensor basis.
+template <int D>
+__device__ __forceinline__ void hermite_contract(const HermCell<D>& C, const double (&Hc)[1 << D][1 << D],
+                                                 double& h, double (&dh)[D]) {
+  constexpr int NM = 1 << D;
+  double val = 0.0, g[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = 0.0;
+#pragma unroll
+  for (int corner = 0; corner < NM; ++corner) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      double wv = 1.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) wv *= C.A[i][(corner >> i) & 1][(m >> i) & 1];
+      val = __builtin_fma(wv, Hc[corner][m], val);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double wg = 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+          wg *= (i == k) ? C.B[i][(corner >> i) & 1][(m >> i) & 1] : C.A[i][(corner >> i) & 1][(m >> i) & 1];
+        g[k] = __builtin_fma(wg, Hc[corner][m], g[k]);
+      }
+    }
+  }
+  h = val;
+#pragma unroll
+  for (int k = 0; k < D; ++k) dh[k] = g[k];
+}
+
 template <int D>
 __device__ __forceinline__ void hermite_eval(const Consts& K, const double* __restrict__ grid,
                                              const double (&s)[D], double& h, double (&dh)[D],
@@ -246,88 +339,20 @@ __device__ __forceinline__ void hermite_eval(const Consts& K, const double* __re
     for (int k = 0; k < D; ++k) dh[k] = src[1 << k];
     return;
   }
-  int64_t j0[D], j1[D];
-  double A[D][2][2], B[D][2][2];   // basis for [cell end][datum: value/derivative]
+  HermCell<D> C;
+  hermite_locate<D>(K, s, C, clamped);
+  double Hc[NM][NM];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const int64_t n = K.grid_n[i];
-    const double dx = K.grid_dx[i];
-    double x = s[i], t;
-    if (K.periodic[i]) {
-      // wrap into one period first, so any finite coordinate lands in a cell
-      double f = (x - K.lo[i]) * K.inv_period[i];
-      f -= floor(f);
-      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
-      const double u = f * (double)n;
-      int64_t j = (int64_t)u;
-      j = j > n - 1 ? n - 1 : j;
-      t = u - (double)j;
-      j0[i] = j;
-      j1[i] = (j + 1 == n) ? 0 : j + 1;
-    } else {
-      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
-      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
-      const double u = (x - K.lo[i]) / dx;
-      int64_t j = (int64_t)u;
-      j = j > n - 2 ? n - 2 : j;
-      j = j < 0 ? 0 : j;
-      t = u - (double)j;
-      j0[i] = j;
-      j1[i] = j + 1;
-    }
-    const double t2 = t * t, t3 = t2 * t;
-    // values of h00, h10 (times dx), h01, h11 (times dx) and their d/ds
-    A[i][0][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
-    A[i][0][1] = (t3 - 2.0 * t2 + t) * dx;
-    A[i][1][0] = -2.0 * t3 + 3.0 * t2;
-    A[i][1][1] = (t3 - t2) * dx;
-    B[i][0][0] = (6.0 * t2 - 6.0 * t) / dx;
-    B[i][0][1] = 3.0 * t2 - 4.0 * t + 1.0;
-    B[i][1][0] = (-6.0 * t2 + 6.0 * t) / dx;
-    B[i][1][1] = 3.0 * t2 - 2.0 * t;
-  }
-  double val = 0.0, g[D];
+  for (int corner = 0; corner < NM; ++corner) {
+    const double* src = grid + hermite_node<D>(K, C, corner) * NM;
 #pragma unroll
-  for (int k = 0; k < D; ++k) g[k] = 0.0;
-#pragma unroll
-  for (int corner = 0; corner < (1 << D); ++corner) {
-    int64_t node = 0, stride = 1;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      node += (((corner >> i) & 1) ? j1[i] : j0[i]) * stride;
-      stride *= K.grid_n[i];
-    }
-    double Hc[NM];
-    const double* src = grid + node * NM;
-    if (NM == 2) {
-      const double2 v = *reinterpret_cast<const double2*>(src);
-      Hc[0] = v.x; Hc[1] = v.y;
-    } else {
-#pragma unroll
-      for (int m = 0; m < NM; m += 2) {
-        const double2 v = *reinterpret_cast<const double2*>(src + m);
-        Hc[m] = v.x; Hc[m + 1] = v.y;
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      double wv = 1.0;
-#pragma unroll
-      for (int i = 0; i < D; ++i) wv *= A[i][(corner >> i) & 1][(m >> i) & 1];
-      val = __builtin_fma(wv, Hc[m], val);
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double wg = 1.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-          wg *= (i == k) ? B[i][(corner >> i) & 1][(m >> i) & 1] : A[i][(corner >> i) & 1][(m >> i) & 1];
-        g[k] = __builtin_fma(wg, Hc[m], g[k]);
-      }
+    for (int m = 0; m < NM; m += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(src + m);
+      Hc[corner][m] = v.x;
+      Hc[corner][m + 1] = v.y;
     }
   }
-  h = val;
-#pragma unroll
-  for (int k = 0; k < D; ++k) dh[k] = g[k];
+  hermite_contract<D>(C, Hc, h, dh);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,6 +401,157 @@ __device__ __forceinline__ int64_t mirror_node_entry(const Consts& K, const int6
 // spacing), an order below the interpolant's own error for grids fine enough
 // to resolve the hills.
 // ---------------------------------------------------------------------------
+// Per axis: the cell (lower node j0, upper j1) and the basis along it, as
+// four weights indexed a = 2 * end + datum (datum 0: value, 1: derivative).
+template <int D> struct HermCell32 {
+  int32_t j0[D], j1[D];
+  float A[D][4], B[D][4];          // interpolant and its derivative d/ds_i
+};
+
+template <int D>
+__device__ __forceinline__ void hermite_locate32(const Consts& K, const double (&s)[D], HermCell32<D>& C,
+                                                 bool& clamped) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int32_t n = K.grid_n[i];
+    const double dx = K.grid_dx[i];
+    double x = s[i], t;
+    if (K.periodic[i]) {
+      double f = (x - K.lo[i]) * K.inv_period[i];
+      f -= floor(f);
+      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
+      const double u = f * (double)n;
+      int32_t j = (int32_t)u;
+      j = j > n - 1 ? n - 1 : j;
+      t = u - (double)j;
+      C.j0[i] = j;
+      C.j1[i] = (j + 1 == n) ? 0 : j + 1;
+    } else {
+      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
+      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
+      const double u = (x - K.lo[i]) / dx;
+      int32_t j = (int32_t)u;
+      j = j > n - 2 ? n - 2 : j;
+      j = j < 0 ? 0 : j;
+      t = u - (double)j;
+      C.j0[i] = j;
+      C.j1[i] = j + 1;
+    }
+    const float tf = (float)t, dxf = (float)dx, idx = (float)(1.0 / dx);
+    const float t2 = tf * tf, t3 = t2 * tf;
+    C.A[i][0] = 2.0f * t3 - 3.0f * t2 + 1.0f;          // lower end, value
+    C.A[i][1] = (t3 - 2.0f * t2 + tf) * dxf;           // lower end, derivative
+    C.A[i][2] = -2.0f * t3 + 3.0f * t2;                // upper end, value
+    C.A[i][3] = (t3 - t2) * dxf;                       // upper end, derivative
+    C.B[i][0] = (6.0f * t2 - 6.0f * tf) * idx;
+    C.B[i][1] = 3.0f * t2 - 4.0f * tf + 1.0f;
+    C.B[i][2] = (-6.0f * t2 + 6.0f * tf) * idx;
+    C.B[i][3] = 3.0f * t2 - 2.0f * tf;
+  }
+}
+
+// The cell's record in the cell-major mirror (1-D, 2-D): 4^D floats, corner c
+// (bit i: upper end along axis i) at 4^D / 2^D * c, its entry m (bit i:
+// derivative along axis i) after it.
+template <int D>
+__device__ __forceinline__ int32_t hermite_cell32(const Consts& K, const HermCell32<D>& C) {
+  static_assert(D <= 2, "cell-major records exist in 1-D and 2-D");
+  int32_t cell = C.j0[0];
+  if (D == 2) cell += C.j0[D - 1] * K.grid_n[0];
+  return cell;
+}
+
+// Record float e (corner e / 2^D, entry e % 2^D) as its flat index in the
+// contraction tensor M[a0][a1][a2], a_i = 2 * corner bit i + entry bit i.
+template <int D>
+__device__ __forceinline__ constexpr int hermite_slot(int corner, int m) {
+  int at = 0, mul = 1;
+  for (int i = 0; i < D; ++i) {
+    at += (2 * ((corner >> i) & 1) + ((m >> i) & 1)) * mul;
+    mul *= 4;
+  }
+  return at;
+}
+
+// A 1-D or 2-D cell record (4^D floats, as float4s) into the tensor.
+template <int D>
+__device__ __forceinline__ void hermite_unpack32(const float4 (&rec)[(1 << D) * (1 << D) / 4],
+                                                 float (&Mf)[(1 << D) * (1 << D)]) {
+  constexpr int NM = 1 << D;
+#pragma unroll
+  for (int v = 0; v < NM * NM / 4; ++v) {
+    const float rv[4] = {rec[v].x, rec[v].y, rec[v].z, rec[v].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Mf[hermite_slot<D>((4 * v + e) / NM, (4 * v + e) % NM)] = rv[e];
+  }
+}
+
+// Contract axis 0 with its value and derivative weights, then the others.
+template <int D>
+__device__ __forceinline__ void hermite_contract32(const HermCell32<D>& C, const float (&Mf)[(1 << D) * (1 << D)],
+                                                   double& h, double (&dh)[D]) {
+  constexpr int NM = 1 << D;
+  float val = 0.0f, g[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = 0.0f;
+  if (D == 1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      val = __builtin_fmaf(C.A[0][a], Mf[a], val);
+      g[0] = __builtin_fmaf(C.B[0][a], Mf[a], g[0]);
+    }
+  } else {
+    constexpr int R = NM * NM / 4;   // entries left after contracting axis 0
+    float tA[R], tB[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float va = 0.0f, vb = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        va = __builtin_fmaf(C.A[0][a], Mf[4 * r + a], va);
+        vb = __builtin_fmaf(C.B[0][a], Mf[4 * r + a], vb);
+      }
+      tA[r] = va;
+      tB[r] = vb;
+    }
+    if (D == 2) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        val = __builtin_fmaf(C.A[D - 1][b], tA[b], val);
+        g[0] = __builtin_fmaf(C.A[D - 1][b], tB[b], g[0]);
+        g[D - 1] = __builtin_fmaf(C.B[D - 1][b], tA[b], g[D - 1]);
+      }
+    } else {
+      // D == 3: contract axis 1 (r = b + 4 c), then axis 2
+      float uA[4], uB0[4], uB1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          x0 = __builtin_fmaf(C.A[1][b], tA[(b + 4 * c) % R], x0);
+          x1 = __builtin_fmaf(C.A[1][b], tB[(b + 4 * c) % R], x1);
+          x2 = __builtin_fmaf(C.B[1][b], tA[(b + 4 * c) % R], x2);
+        }
+        uA[c] = x0;
+        uB0[c] = x1;
+        uB1[c] = x2;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k2 = D - 1;
+        val = __builtin_fmaf(C.A[k2][c], uA[c], val);
+        g[0] = __builtin_fmaf(C.A[k2][c], uB0[c], g[0]);
+        g[1 % D] = __builtin_fmaf(C.A[k2][c], uB1[c], g[1 % D]);
+        g[k2] = __builtin_fmaf(C.B[k2][c], uA[c], g[k2]);
+      }
+    }
+  }
+  h = (double)val;
+#pragma unroll
+  for (int k = 0; k < D; ++k) dh[k] = (double)g[k];
+}
+
 template <int D>
 __device__ __forceinline__ void hermite_eval32(const Consts& K, const float* __restrict__ grid,
                                                const double (&s)[D], double& h, double (&dh)[D], bool& clamped) {
@@ -393,77 +569,23 @@ __device__ __forceinline__ void hermite_eval32(const Consts& K, const float* __r
     for (int k = 0; k < D; ++k) dh[k] = (double)grid[mirror_node_entry(K, j, 1 << k)];
     return;
   }
-  // per axis: the cell (lower node j0, upper j1) and the basis along it, as
-  // four weights indexed a = 2 * end + datum (datum 0: value, 1: derivative)
-  int32_t j0[D], j1[D];
-  float A[D][4], B[D][4];          // interpolant and its derivative d/ds_i
+  HermCell32<D> C;
+  hermite_locate32<D>(K, s, C, clamped);
+  // the cell's data: one cell record (1-D, 2-D) or 2^D node records (3-D)
+  float Mf[NM * NM];
+  if constexpr (D <= 2) {
+    const float4* src = reinterpret_cast<const float4*>(grid + (int64_t)hermite_cell32<D>(K, C) * (NM * NM));
+    float4 rec[NM * NM / 4];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const int32_t n = K.grid_n[i];
-    const double dx = K.grid_dx[i];
-    double x = s[i], t;
-    if (K.periodic[i]) {
-      double f = (x - K.lo[i]) * K.inv_period[i];
-      f -= floor(f);
-      if (!(f >= 0.0 && f < 1.0)) f = 0.0;          // non-finite input
-      const double u = f * (double)n;
-      int32_t j = (int32_t)u;
-      j = j > n - 1 ? n - 1 : j;
-      t = u - (double)j;
-      j0[i] = j;
-      j1[i] = (j + 1 == n) ? 0 : j + 1;
-    } else {
-      if (!(x >= K.lo[i])) { x = K.lo[i]; clamped = true; }   // also catches NaN
-      if (x > K.hi[i]) { x = K.hi[i]; clamped = true; }
-      const double u = (x - K.lo[i]) / dx;
-      int32_t j = (int32_t)u;
-      j = j > n - 2 ? n - 2 : j;
-      j = j < 0 ? 0 : j;
-      t = u - (double)j;
-      j0[i] = j;
-      j1[i] = j + 1;
-    }
-    const float tf = (float)t, dxf = (float)dx, idx = (float)(1.0 / dx);
-    const float t2 = tf * tf, t3 = t2 * tf;
-    A[i][0] = 2.0f * t3 - 3.0f * t2 + 1.0f;          // lower end, value
-    A[i][1] = (t3 - 2.0f * t2 + tf) * dxf;           // lower end, derivative
-    A[i][2] = -2.0f * t3 + 3.0f * t2;                // upper end, value
-    A[i][3] = (t3 - t2) * dxf;                       // upper end, derivative
-    B[i][0] = (6.0f * t2 - 6.0f * tf) * idx;
-    B[i][1] = 3.0f * t2 - 4.0f * tf + 1.0f;
-    B[i][2] = (-6.0f * t2 + 6.0f * tf) * idx;
-    B[i][3] = 3.0f * t2 - 2.0f * tf;
-  }
-  // the cell's data as a tensor M[a0][a1][a2] (a_i = 2 * corner bit i + entry
-  // bit i): one cell record (1-D, 2-D) or 2^D node records (3-D)
-  float Mf[NM * NM];               // flat, index sum_i a_i 4^i
-  auto put = [&](int corner, int m, float v) {
-    int at = 0, mul = 1;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      at += (2 * ((corner >> i) & 1) + ((m >> i) & 1)) * mul;
-      mul *= 4;
-    }
-    Mf[at] = v;
-  };
-  if (D <= 2) {
-    int32_t cell = j0[0];
-    if (D == 2) cell += j0[D - 1] * K.grid_n[0];
-    const float4* src = reinterpret_cast<const float4*>(grid + (int64_t)cell * (NM * NM));
-#pragma unroll
-    for (int v = 0; v < NM * NM / 4; ++v) {
-      const float4 r = src[v];
-      const float rv[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) put((4 * v + e) / NM, (4 * v + e) % NM, rv[e]);
-    }
+    for (int v = 0; v < NM * NM / 4; ++v) rec[v] = src[v];
+    hermite_unpack32<D>(rec, Mf);
   } else {
 #pragma unroll
     for (int c = 0; c < NM; ++c) {
       int64_t node = 0, stride = 1;
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        node += (((c >> i) & 1) ? j1[i] : j0[i]) * stride;
+        node += (((c >> i) & 1) ? C.j1[i] : C.j0[i]) * stride;
         stride *= K.grid_n[i];
       }
       const float4* src = reinterpret_cast<const float4*>(grid + node * NM);
@@ -472,70 +594,11 @@ __device__ __forceinline__ void hermite_eval32(const Consts& K, const float* __r
         const float4 r = src[v];
         const float rv[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) put(c, 4 * v + e, rv[e]);
+        for (int e = 0; e < 4; ++e) Mf[hermite_slot<D>(c, 4 * v + e)] = rv[e];
       }
     }
   }
-  // contract axis 0 with its value and derivative weights, then the others
-  float val = 0.0f, g[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) g[k] = 0.0f;
-  if (D == 1) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      val = __builtin_fmaf(A[0][a], Mf[a], val);
-      g[0] = __builtin_fmaf(B[0][a], Mf[a], g[0]);
-    }
-  } else {
-    constexpr int R = NM * NM / 4;   // entries left after contracting axis 0
-    float tA[R], tB[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float va = 0.0f, vb = 0.0f;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        va = __builtin_fmaf(A[0][a], Mf[4 * r + a], va);
-        vb = __builtin_fmaf(B[0][a], Mf[4 * r + a], vb);
-      }
-      tA[r] = va;
-      tB[r] = vb;
-    }
-    if (D == 2) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        val = __builtin_fmaf(A[D - 1][b], tA[b], val);
-        g[0] = __builtin_fmaf(A[D - 1][b], tB[b], g[0]);
-        g[D - 1] = __builtin_fmaf(B[D - 1][b], tA[b], g[D - 1]);
-      }
-    } else {
-      // D == 3: contract axis 1 (r = b + 4 c), then axis 2
-      float uA[4], uB0[4], uB1[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          x0 = __builtin_fmaf(A[1][b], tA[(b + 4 * c) % R], x0);
-          x1 = __builtin_fmaf(A[1][b], tB[(b + 4 * c) % R], x1);
-          x2 = __builtin_fmaf(B[1][b], tA[(b + 4 * c) % R], x2);
-        }
-        uA[c] = x0;
-        uB0[c] = x1;
-        uB1[c] = x2;
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int k2 = D - 1;
-        val = __builtin_fmaf(A[k2][c], uA[c], val);
-        g[0] = __builtin_fmaf(A[k2][c], uB0[c], g[0]);
-        g[1 % D] = __builtin_fmaf(A[k2][c], uB1[c], g[1 % D]);
-        g[k2] = __builtin_fmaf(B[k2][c], uA[c], g[k2]);
-      }
-    }
-  }
-  h = (double)val;
-#pragma unroll
-  for (int k = 0; k < D; ++k) dh[k] = (double)g[k];
+  hermite_contract32<D>(C, Mf, h, dh);
 }
 
 // ---------------------------------------------------------------------------

@@ -499,9 +499,9 @@ struct EvalArgs {
 };
 
 // Queries per thread: independent corner gathers in flight (1-D/2-D); the
-// 3-D interpolation is register-heavy enough on its own. From the FP32
-// mirror two queries per thread were fastest (2-D, 1,048,576 queries: 17.9,
-// 15.5 and 17.0 us for one, two and four).
+// 3-D interpolation is register-heavy enough on its own. In 2-D this kernel
+// serves the quantised look-up (and FP64 grids past 2^31 nodes); the Hermite
+// interpolation has the group-of-four kernels below.
 template <int D, class T> struct EvalQ { static constexpr int value = D == 3 ? 1 : (sizeof(T) == 4 ? 2 : 4); };
 
 template <int D, class T>
@@ -551,6 +551,160 @@ __global__ __launch_bounds__(kBlock) void k_grid_eval(const EvalArgs A) {
       for (int i = 0; i < D; ++i) static_cast<float*>(A.dV)[i * A.nq + j] = (float)dV[i];
     }
   }
+}
+
+// Lane r's value of each group of four lanes, to all four (DPP quad_perm
+// r,r,r,r). Every lane of the wave must be active where it runs.
+template <int R>
+__device__ __forceinline__ int32_t quad_lane(int32_t v) {
+  return __builtin_amdgcn_mov_dpp(v, R * 0x55, 0xF, 0xF, true);
+}
+
+template <int R>
+__device__ __forceinline__ void quad_lanes(const int32_t (&v)[4], int32_t (&out)[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[c] = quad_lane<R>(v[c]);
+}
+
+// A query's outputs from the interpolated h and dh/ds: NaN for a non-finite
+// query coordinate, the transform, FP32 or FP64 stores.
+template <int D>
+__device__ __forceinline__ void store_query(const EvalArgs& A, int64_t j, double h, double (&dh)[D], bool clamped,
+                                            bool finite) {
+  if (!finite) {
+    clamped = false;
+    h = __builtin_nan("");
+#pragma unroll
+    for (int i = 0; i < D; ++i) dh[i] = h;
+  }
+  if (clamped && A.n_clamped) atomicAdd(A.n_clamped, 1ull);
+  double V, dV[D];
+  apply_transform<D>(A.K, h, dh, V, dV);
+  if (A.q_f64) {
+    static_cast<double*>(A.V)[j] = V;
+#pragma unroll
+    for (int i = 0; i < D; ++i) static_cast<double*>(A.dV)[i * A.nq + j] = dV[i];
+  } else {
+    static_cast<float*>(A.V)[j] = (float)V;
+#pragma unroll
+    for (int i = 0; i < D; ++i) static_cast<float*>(A.dV)[i * A.nq + j] = (float)dV[i];
+  }
+}
+
+// 2-D interpolation from the FP32 cell-major mirror, the 64-byte cell records
+// fetched by groups of four lanes: in round r, lane p of a group loads the
+// p-th 16 bytes of the record of the query that the group's lane r holds, so
+// one load instruction reaches 16 records, a whole 64-byte piece of each,
+// rather than 16 bytes of 64 records; the pieces pass through LDS to the lane
+// that holds the query, which interpolates as hermite_eval32 does (the same
+// arithmetic in the same order). 2-D, 1,048,576 queries: 11.4 us against
+// 14.0 us for two queries a thread each loading its own records; two queries
+// a lane here: 13.7 us.
+__global__ __launch_bounds__(kBlock) void k_grid_eval_cells32(const EvalArgs A) {
+  constexpr int kRound = 65;           // float4 per wave and round: 64 pieces, + 1 so the owners' reads spread over the banks
+  __shared__ float4 pieces[kBlock / 64][4][kRound];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane & 3, grp = lane >> 2;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t jq = j < A.nq ? j : A.nq - 1;      // every lane takes part in the rounds
+  double s[2];
+  bool finite = true, clamped = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    s[i] = A.q_f64 ? static_cast<const double*>(A.q)[i * A.nq + jq]
+                   : (double)static_cast<const float*>(A.q)[i * A.nq + jq];
+    finite = finite && isfinite(s[i]);
+  }
+  HermCell32<2> C;
+  hermite_locate32<2>(A.K, s, C, clamped);
+  const int32_t cell = hermite_cell32<2>(A.K, C);
+  // record float4 p of each cell is corner p's four entries
+  const float4* rec = reinterpret_cast<const float4*>(A.grid32);
+  const float4 r0 = rec[(int64_t)quad_lane<0>(cell) * 4 + p], r1 = rec[(int64_t)quad_lane<1>(cell) * 4 + p];
+  const float4 r2 = rec[(int64_t)quad_lane<2>(cell) * 4 + p], r3 = rec[(int64_t)quad_lane<3>(cell) * 4 + p];
+  pieces[wave][0][4 * grp + p] = r0;
+  pieces[wave][1][4 * grp + p] = r1;
+  pieces[wave][2][4 * grp + p] = r2;
+  pieces[wave][3][4 * grp + p] = r3;
+  __syncthreads();
+  float4 own[4];                       // this lane's query was fetched in round p
+#pragma unroll
+  for (int v = 0; v < 4; ++v) own[v] = pieces[wave][p][4 * grp + v];
+  float Mf[16];
+  hermite_unpack32<2>(own, Mf);
+  double h, dh[2];
+  hermite_contract32<2>(C, Mf, h, dh);
+  if (j < A.nq) store_query<2>(A, j, h, dh, clamped, finite);
+}
+
+// 2-D interpolation from the FP64 node arrays (four doubles, 32 bytes, a
+// node), the four nodes of a query fetched by groups of four lanes: in round
+// r the group reads the two rows of the cell of the query that its lane r
+// holds, 64 contiguous bytes each (two adjacent nodes), lane p taking the
+// p-th 16 bytes of each row; a load instruction then reaches 16 node pairs,
+// mostly one line each, rather than 16 bytes of 64 scattered nodes. The pieces
+// pass through LDS to the lane that holds the query, which interpolates as
+// hermite_eval does. 2-D, 1,048,576 queries: 19.5 us against 23.0 us for
+// four queries a thread each loading its own nodes.
+__global__ __launch_bounds__(kBlock) void k_grid_eval_nodes64(const EvalArgs A) {
+  constexpr int kRound = 129;          // double2 per wave and round: 128 pieces, + 1 so the owners' reads spread over the banks
+  __shared__ double2 pieces[kBlock / 64][4][kRound];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, p = lane & 3, grp = lane >> 2;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t jq = j < A.nq ? j : A.nq - 1;      // every lane takes part in the rounds
+  double s[2];
+  bool finite = true, clamped = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    s[i] = A.q_f64 ? static_cast<const double*>(A.q)[i * A.nq + jq]
+                   : (double)static_cast<const float*>(A.q)[i * A.nq + jq];
+    finite = finite && isfinite(s[i]);
+  }
+  HermCell<2> C;
+  hermite_locate<2>(A.K, s, C, clamped);
+  int32_t nd[4];                       // corner c's node (bit 0: upper x end, bit 1: upper y end)
+#pragma unroll
+  for (int c = 0; c < 4; ++c) nd[c] = (int32_t)hermite_node<2>(A.K, C, c);
+  const double2* g2 = reinterpret_cast<const double2*>(A.grid);
+  // round r: this lane's node in each row of the cell of lane r's query (the
+  // broadcasts run in every lane, before any lane-dependent choice)
+  int32_t b0[4], b1[4], b2[4], b3[4];
+  quad_lanes<0>(nd, b0);
+  quad_lanes<1>(nd, b1);
+  quad_lanes<2>(nd, b2);
+  quad_lanes<3>(nd, b3);
+  const bool upper_x = (p >> 1) != 0;
+  const int32_t l0 = upper_x ? b0[1] : b0[0], u0 = upper_x ? b0[3] : b0[2];
+  const int32_t l1 = upper_x ? b1[1] : b1[0], u1 = upper_x ? b1[3] : b1[2];
+  const int32_t l2 = upper_x ? b2[1] : b2[0], u2 = upper_x ? b2[3] : b2[2];
+  const int32_t l3 = upper_x ? b3[1] : b3[0], u3 = upper_x ? b3[3] : b3[2];
+  const int half = p & 1;
+  const double2 gl0 = g2[(int64_t)l0 * 2 + half], gu0 = g2[(int64_t)u0 * 2 + half];
+  const double2 gl1 = g2[(int64_t)l1 * 2 + half], gu1 = g2[(int64_t)u1 * 2 + half];
+  const double2 gl2 = g2[(int64_t)l2 * 2 + half], gu2 = g2[(int64_t)u2 * 2 + half];
+  const double2 gl3 = g2[(int64_t)l3 * 2 + half], gu3 = g2[(int64_t)u3 * 2 + half];
+  pieces[wave][0][8 * grp + p] = gl0;
+  pieces[wave][0][8 * grp + 4 + p] = gu0;
+  pieces[wave][1][8 * grp + p] = gl1;
+  pieces[wave][1][8 * grp + 4 + p] = gu1;
+  pieces[wave][2][8 * grp + p] = gl2;
+  pieces[wave][2][8 * grp + 4 + p] = gu2;
+  pieces[wave][3][8 * grp + p] = gl3;
+  pieces[wave][3][8 * grp + 4 + p] = gu3;
+  __syncthreads();
+  // this lane's query was fetched in round p; piece 2 c + half holds corner
+  // c's entries 2 half and 2 half + 1
+  double Hc[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const double2 v = pieces[wave][p][8 * grp + 2 * c + half];
+      Hc[c][2 * half] = v.x;
+      Hc[c][2 * half + 1] = v.y;
+    }
+  double h, dh[2];
+  hermite_contract<2>(C, Hc, h, dh);
+  if (j < A.nq) store_query<2>(A, j, h, dh, clamped, finite);
 }
 
 template <int D>
@@ -680,8 +834,15 @@ hipError_t launch_grid_eval(const Consts& K, const double* grid, const float* gr
   switch (K.ndim * 2 + (grid32 ? 1 : 0)) {
     case 2: hipLaunchKernelGGL((k_grid_eval<1, double>), dim3(blocks(EvalQ<1, double>::value)), t, 0, stream, A); break;
     case 3: hipLaunchKernelGGL((k_grid_eval<1, float>), dim3(blocks(EvalQ<1, float>::value)), t, 0, stream, A); break;
-    case 4: hipLaunchKernelGGL((k_grid_eval<2, double>), dim3(blocks(EvalQ<2, double>::value)), t, 0, stream, A); break;
-    case 5: hipLaunchKernelGGL((k_grid_eval<2, float>), dim3(blocks(EvalQ<2, float>::value)), t, 0, stream, A); break;
+    case 4:
+      if (K.quant || K.nodes >= ((int64_t)1 << 31))
+        hipLaunchKernelGGL((k_grid_eval<2, double>), dim3(blocks(EvalQ<2, double>::value)), t, 0, stream, A);
+      else hipLaunchKernelGGL(k_grid_eval_nodes64, dim3(blocks(1)), t, 0, stream, A);
+      break;
+    case 5:
+      if (K.quant) hipLaunchKernelGGL((k_grid_eval<2, float>), dim3(blocks(EvalQ<2, float>::value)), t, 0, stream, A);
+      else hipLaunchKernelGGL(k_grid_eval_cells32, dim3(blocks(1)), t, 0, stream, A);
+      break;
     case 6: hipLaunchKernelGGL((k_grid_eval<3, double>), dim3(blocks(EvalQ<3, double>::value)), t, 0, stream, A); break;
     case 7: hipLaunchKernelGGL((k_grid_eval<3, float>), dim3(blocks(EvalQ<3, float>::value)), t, 0, stream, A); break;
     default: return hipErrorInvalidValue;
