@@ -262,15 +262,15 @@ __device__ __forceinline__ void hermite_locate(const Consts& K, const double (&s
       C.j0[i] = j;
       C.j1[i] = j + 1;
     }
-    const double t2 = t * t, t3 = t2 * t;
+    const double t2 = t * t, t3 = t2 * t, idx = K.inv_grid_dx[i];
     // values of h00, h10 (times dx), h01, h11 (times dx) and their d/ds
     C.A[i][0][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
     C.A[i][0][1] = (t3 - 2.0 * t2 + t) * dx;
     C.A[i][1][0] = -2.0 * t3 + 3.0 * t2;
     C.A[i][1][1] = (t3 - t2) * dx;
-    C.B[i][0][0] = (6.0 * t2 - 6.0 * t) / dx;
+    C.B[i][0][0] = (6.0 * t2 - 6.0 * t) * idx;
     C.B[i][0][1] = 3.0 * t2 - 4.0 * t + 1.0;
-    C.B[i][1][0] = (-6.0 * t2 + 6.0 * t) / dx;
+    C.B[i][1][0] = (-6.0 * t2 + 6.0 * t) * idx;
     C.B[i][1][1] = 3.0 * t2 - 2.0 * t;
   }
 }
@@ -437,7 +437,7 @@ __device__ __forceinline__ void hermite_locate32(const Consts& K, const double (
       C.j0[i] = j;
       C.j1[i] = j + 1;
     }
-    const float tf = (float)t, dxf = (float)dx, idx = (float)(1.0 / dx);
+    const float tf = (float)t, dxf = (float)dx, idx = (float)K.inv_grid_dx[i];
     const float t2 = tf * tf, t3 = t2 * tf;
     C.A[i][0] = 2.0f * t3 - 3.0f * t2 + 1.0f;          // lower end, value
     C.A[i][1] = (t3 - 2.0f * t2 + tf) * dxf;           // lower end, derivative

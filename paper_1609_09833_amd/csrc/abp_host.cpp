@@ -175,6 +175,7 @@ void make_consts(const abp_bias_desc& d, Consts& K) {
     K.grid_n[i] = d.grid_n[i];
     if (d.grid_n[i] > 0) {
       K.grid_dx[i] = per ? L / d.grid_n[i] : L / (d.grid_n[i] - 1);
+      K.inv_grid_dx[i] = 1.0 / K.grid_dx[i];
       K.nodes *= d.grid_n[i];
     }
   }

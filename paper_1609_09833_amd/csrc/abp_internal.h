@@ -60,6 +60,7 @@ struct Consts {
   // grid
   int32_t grid_n[3];
   double grid_dx[3];               // node spacing per axis
+  double inv_grid_dx[3];           // 1 / grid_dx (correctly rounded, as a device division would give)
   int64_t nodes;
 };
 
