@@ -225,11 +225,11 @@ __device__ __forceinline__ void apply_transform(const Consts& K, double h, const
 // Returns h and the analytic gradient; *clamped is set when a non-periodic
 // coordinate lay outside [lo, hi].
 // ---------------------------------------------------------------------------
-// Per axis: the cell (lower node j0, upper j1) and the basis along it, for
-// [cell end][datum: value/derivative].
+// Per axis: the cell (lower node j0, upper j1) and the basis along it, as
+// four weights indexed a = 2 * end + datum (datum 0: value, 1: derivative).
 template <int D> struct HermCell {
   int64_t j0[D], j1[D];
-  double A[D][2][2], B[D][2][2];   // interpolant and its derivative d/ds_i
+  double A[D][4], B[D][4];         // interpolant and its derivative d/ds_i, [2 * end + datum]
 };
 
 template <int D>
@@ -264,14 +264,14 @@ __device__ __forceinline__ void hermite_locate(const Consts& K, const double (&s
     }
     const double t2 = t * t, t3 = t2 * t, idx = K.inv_grid_dx[i];
     // values of h00, h10 (times dx), h01, h11 (times dx) and their d/ds
-    C.A[i][0][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
-    C.A[i][0][1] = (t3 - 2.0 * t2 + t) * dx;
-    C.A[i][1][0] = -2.0 * t3 + 3.0 * t2;
-    C.A[i][1][1] = (t3 - t2) * dx;
-    C.B[i][0][0] = (6.0 * t2 - 6.0 * t) * idx;
-    C.B[i][0][1] = 3.0 * t2 - 4.0 * t + 1.0;
-    C.B[i][1][0] = (-6.0 * t2 + 6.0 * t) * idx;
-    C.B[i][1][1] = 3.0 * t2 - 2.0 * t;
+    C.A[i][0] = 2.0 * t3 - 3.0 * t2 + 1.0;
+    C.A[i][1] = (t3 - 2.0 * t2 + t) * dx;
+    C.A[i][2] = -2.0 * t3 + 3.0 * t2;
+    C.A[i][3] = (t3 - t2) * dx;
+    C.B[i][0] = (6.0 * t2 - 6.0 * t) * idx;
+    C.B[i][1] = 3.0 * t2 - 4.0 * t + 1.0;
+    C.B[i][2] = (-6.0 * t2 + 6.0 * t) * idx;
+    C.B[i][3] = 3.0 * t2 - 2.0 * t;
   }
 }
 
@@ -287,35 +287,96 @@ __device__ __forceinline__ int64_t hermite_node(const Consts& K, const HermCell<
   return node;
 }
 
-// Sum over the corners' node values Hc[corner][entry] with the tensor basis.
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Record entry m of corner c as its flat index in the contraction tensor
+// M[a0][a1][a2], a_i = 2 * corner bit i + entry bit i.
+template <int D>
+__device__ __forceinline__ constexpr int hermite_slot(int corner, int m) {
+  int at = 0, mul = 1;
+  for (int i = 0; i < D; ++i) {
+    at += (2 * ((corner >> i) & 1) + ((m >> i) & 1)) * mul;
+    mul *= 4;
+  }
+  return at;
+}
+
+// The tensor-product sum: contract axis 0 of M with its value and derivative
+// weights, then the other axes, giving the interpolant and its gradient.
+template <int D, class T>
+__device__ __forceinline__ void hermite_contract_axes(const T (&A)[D][4], const T (&B)[D][4],
+                                                      const T (&Mf)[(1 << D) * (1 << D)], T& val, T (&g)[D]) {
+  constexpr int NM = 1 << D;
+  val = T(0);
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = T(0);
+  if (D == 1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      val = fma_of(A[0][a], Mf[a], val);
+      g[0] = fma_of(B[0][a], Mf[a], g[0]);
+    }
+  } else {
+    constexpr int R = NM * NM / 4;   // entries left after contracting axis 0
+    T tA[R], tB[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T va = T(0), vb = T(0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        va = fma_of(A[0][a], Mf[4 * r + a], va);
+        vb = fma_of(B[0][a], Mf[4 * r + a], vb);
+      }
+      tA[r] = va;
+      tB[r] = vb;
+    }
+    if (D == 2) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        val = fma_of(A[D - 1][b], tA[b], val);
+        g[0] = fma_of(A[D - 1][b], tB[b], g[0]);
+        g[D - 1] = fma_of(B[D - 1][b], tA[b], g[D - 1]);
+      }
+    } else {
+      // D == 3: contract axis 1 (r = b + 4 c), then axis 2
+      T uA[4], uB0[4], uB1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T x0 = T(0), x1 = T(0), x2 = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          x0 = fma_of(A[1][b], tA[(b + 4 * c) % R], x0);
+          x1 = fma_of(A[1][b], tB[(b + 4 * c) % R], x1);
+          x2 = fma_of(B[1][b], tA[(b + 4 * c) % R], x2);
+        }
+        uA[c] = x0;
+        uB0[c] = x1;
+        uB1[c] = x2;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k2 = D - 1;
+        val = fma_of(A[k2][c], uA[c], val);
+        g[0] = fma_of(A[k2][c], uB0[c], g[0]);
+        g[1 % D] = fma_of(A[k2][c], uB1[c], g[1 % D]);
+        g[k2] = fma_of(B[k2][c], uA[c], g[k2]);
+      }
+    }
+  }
+}
+
+// The corners' node values Hc[corner][entry] through the tensor basis.
 template <int D>
 __device__ __forceinline__ void hermite_contract(const HermCell<D>& C, const double (&Hc)[1 << D][1 << D],
                                                  double& h, double (&dh)[D]) {
   constexpr int NM = 1 << D;
-  double val = 0.0, g[D];
+  double Mf[NM * NM];
 #pragma unroll
-  for (int k = 0; k < D; ++k) g[k] = 0.0;
+  for (int c = 0; c < NM; ++c)
 #pragma unroll
-  for (int corner = 0; corner < NM; ++corner) {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      double wv = 1.0;
-#pragma unroll
-      for (int i = 0; i < D; ++i) wv *= C.A[i][(corner >> i) & 1][(m >> i) & 1];
-      val = __builtin_fma(wv, Hc[corner][m], val);
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double wg = 1.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-          wg *= (i == k) ? C.B[i][(corner >> i) & 1][(m >> i) & 1] : C.A[i][(corner >> i) & 1][(m >> i) & 1];
-        g[k] = __builtin_fma(wg, Hc[corner][m], g[k]);
-      }
-    }
-  }
-  h = val;
-#pragma unroll
-  for (int k = 0; k < D; ++k) dh[k] = g[k];
+    for (int m = 0; m < NM; ++m) Mf[hermite_slot<D>(c, m)] = Hc[c][m];
+  hermite_contract_axes<D, double>(C.A, C.B, Mf, h, dh);
 }
 
 template <int D>
@@ -461,18 +522,6 @@ __device__ __forceinline__ int32_t hermite_cell32(const Consts& K, const HermCel
   return cell;
 }
 
-// Record float e (corner e / 2^D, entry e % 2^D) as its flat index in the
-// contraction tensor M[a0][a1][a2], a_i = 2 * corner bit i + entry bit i.
-template <int D>
-__device__ __forceinline__ constexpr int hermite_slot(int corner, int m) {
-  int at = 0, mul = 1;
-  for (int i = 0; i < D; ++i) {
-    at += (2 * ((corner >> i) & 1) + ((m >> i) & 1)) * mul;
-    mul *= 4;
-  }
-  return at;
-}
-
 // A 1-D or 2-D cell record (4^D floats, as float4s) into the tensor.
 template <int D>
 __device__ __forceinline__ void hermite_unpack32(const float4 (&rec)[(1 << D) * (1 << D) / 4],
@@ -486,67 +535,12 @@ __device__ __forceinline__ void hermite_unpack32(const float4 (&rec)[(1 << D) * 
   }
 }
 
-// Contract axis 0 with its value and derivative weights, then the others.
+// The FP32 tensor-product sum, returned in FP64.
 template <int D>
 __device__ __forceinline__ void hermite_contract32(const HermCell32<D>& C, const float (&Mf)[(1 << D) * (1 << D)],
                                                    double& h, double (&dh)[D]) {
-  constexpr int NM = 1 << D;
-  float val = 0.0f, g[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) g[k] = 0.0f;
-  if (D == 1) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      val = __builtin_fmaf(C.A[0][a], Mf[a], val);
-      g[0] = __builtin_fmaf(C.B[0][a], Mf[a], g[0]);
-    }
-  } else {
-    constexpr int R = NM * NM / 4;   // entries left after contracting axis 0
-    float tA[R], tB[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float va = 0.0f, vb = 0.0f;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        va = __builtin_fmaf(C.A[0][a], Mf[4 * r + a], va);
-        vb = __builtin_fmaf(C.B[0][a], Mf[4 * r + a], vb);
-      }
-      tA[r] = va;
-      tB[r] = vb;
-    }
-    if (D == 2) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        val = __builtin_fmaf(C.A[D - 1][b], tA[b], val);
-        g[0] = __builtin_fmaf(C.A[D - 1][b], tB[b], g[0]);
-        g[D - 1] = __builtin_fmaf(C.B[D - 1][b], tA[b], g[D - 1]);
-      }
-    } else {
-      // D == 3: contract axis 1 (r = b + 4 c), then axis 2
-      float uA[4], uB0[4], uB1[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          x0 = __builtin_fmaf(C.A[1][b], tA[(b + 4 * c) % R], x0);
-          x1 = __builtin_fmaf(C.A[1][b], tB[(b + 4 * c) % R], x1);
-          x2 = __builtin_fmaf(C.B[1][b], tA[(b + 4 * c) % R], x2);
-        }
-        uA[c] = x0;
-        uB0[c] = x1;
-        uB1[c] = x2;
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int k2 = D - 1;
-        val = __builtin_fmaf(C.A[k2][c], uA[c], val);
-        g[0] = __builtin_fmaf(C.A[k2][c], uB0[c], g[0]);
-        g[1 % D] = __builtin_fmaf(C.A[k2][c], uB1[c], g[1 % D]);
-        g[k2] = __builtin_fmaf(C.B[k2][c], uA[c], g[k2]);
-      }
-    }
-  }
+  float val, g[D];
+  hermite_contract_axes<D, float>(C.A, C.B, Mf, val, g);
   h = (double)val;
 #pragma unroll
   for (int k = 0; k < D; ++k) dh[k] = (double)g[k];
