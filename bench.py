@@ -35,7 +35,7 @@ FP32_NONPACKED_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12   # FMA on every lane, no 
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE (x 2,
 # copy-calibrated) and WRITE_SIZE (x 1), valid only for the kernel sources
 # they were taken on.
-HEADLINE_TRAFFIC = {"sources_sha256": "e4710bfb3eafef5c960f7543e5eda46ad6c71f769ba275d668dff445acdad543", "fetch_kib": 7305.5, "write_kib": 12288.0,
+HEADLINE_TRAFFIC = {"sources_sha256": "d0bd6a969ad4991586539920b6e5d502a960f9ba454a64d35bb20db5d41036bb", "fetch_kib": 7305.6, "write_kib": 12288.0,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 HEADLINE_SOURCES = ("paper_1609_09833_amd/csrc/direct_sum_impl.h", "paper_1609_09833_amd/csrc/direct_sum_d2.hip",
                     "paper_1609_09833_amd/csrc/direct_sum.hip", "paper_1609_09833_amd/csrc/abp_device.h",
