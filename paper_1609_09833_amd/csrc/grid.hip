@@ -498,11 +498,12 @@ struct EvalArgs {
   unsigned long long* n_clamped;
 };
 
-// Queries per thread: independent corner gathers in flight (1-D/2-D); the
-// 3-D interpolation is register-heavy enough on its own. In 2-D this kernel
-// serves the quantised look-up (and FP64 grids past 2^31 nodes); the Hermite
-// interpolation has the group-of-four kernels below.
-template <int D, class T> struct EvalQ { static constexpr int value = D == 3 ? 1 : (sizeof(T) == 4 ? 2 : 4); };
+// Queries per thread: independent corner gathers in flight (1-D); the 3-D
+// interpolation is register-heavy enough on its own. In 2-D this kernel
+// serves the quantised look-up (and grids past 2^31 nodes), one query a
+// thread (480^2 paper grid, 1,048,576 look-ups: 13.6 us against 15.7 us with
+// four); the Hermite interpolation has the group-of-four kernels below.
+template <int D, class T> struct EvalQ { static constexpr int value = D >= 2 ? 1 : (sizeof(T) == 4 ? 2 : 4); };
 
 template <int D, class T>
 __global__ __launch_bounds__(kBlock) void k_grid_eval(const EvalArgs A) {
