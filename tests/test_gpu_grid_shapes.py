@@ -176,3 +176,56 @@ def test_compact_deposits_refresh_the_mirror_where_they_land(ndim, grid_n, quant
         gscale = max(np.abs(dV64).max(), 1e-30)
         assert np.abs(dV32 - dV64).max() <= 1e-4 * gscale, (k, np.abs(dV32 - dV64).max(), gscale)
     _check(spec, abp.abp_grid_export(ctx), hills)
+
+
+@pytest.mark.parametrize("periodic,grid_n", [((1, 1), (2, 3)), ((0, 0), (2, 2)), ((1, 0), (33, 2)),
+                                             ((0, 1), (31, 65)), ((1, 1), (64, 32))])
+def test_grid_eval_ragged_batches_and_cell_edges(periodic, grid_n):
+    """2-D Hermite evaluation (four lanes fetch one query's cell data and hand
+    it over through LDS): batches that end inside a group of four and inside a
+    wave, queries on nodes, on the upper end of a non-periodic axis and
+    outside it, in both precisions and both query types, against the
+    oracle's interpolation; and every query's result the same, bit for bit,
+    whichever batch (and lane) it is evaluated in."""
+    from paper_1609_09833_amd import abp
+    from tests.tolerance import check_bound
+    device()
+    spec = _spec(2, periodic, grid_n)
+    hills = _hills(spec, 40, 17 + grid_n[0])
+    ctx = abp.Context(spec, capacity=hills.n)
+    abp.bias_deposit(ctx, to_dev(hills.centers), to_dev(hills.heights))
+    Ho = oracle.grid_all(spec, hills.centers, hills.heights)
+    rng = np.random.default_rng(grid_n[0] * 7 + grid_n[1])
+    n = 257
+    q = np.vstack([rng.uniform(spec.lo[i] - 0.2, spec.hi[i] + 0.2, n) for i in range(2)])
+    dx = [(spec.hi[i] - spec.lo[i]) / (grid_n[i] if periodic[i] else grid_n[i] - 1) for i in range(2)]
+    for i in range(2):                   # nodes, and the upper end of the range
+        q[i, :16] = spec.lo[i] + dx[i] * rng.integers(0, grid_n[i], 16)
+        q[i, 16:20] = spec.hi[i]
+    _, _, A0, A = oracle.hill_sum(spec, hills.centers, hills.heights, q)
+    gscale = float(np.abs(Ho).max()) * max(1.0, max(dx)) ** 2
+    for qdt in (np.float64, np.float32):
+        qq = q.astype(qdt)
+        hq, dhq, _ = oracle.grid_eval(spec, Ho, qq.astype(np.float64))
+        for prec in (abp.ABP_PREC_FP64, abp.ABP_PREC_FP32_KAHAN):
+            fp64 = prec == abp.ABP_PREC_FP64
+            full = None
+            for m in (1, 3, 5, 63, 65, 257):
+                V, dV = abp.bias_eval(ctx, to_dev(qq[:, :m]), mode=abp.ABP_EVAL_GRID, prec=prec)
+                abp.abp_sync(ctx)
+                V, dV = V.cpu().numpy(), dV.cpu().numpy()
+                if full is None or m == 257:
+                    tol = (1e-9 if qdt == np.float64 else 1e-6) if fp64 else 1e-6
+                    floor = (1e-13 if fp64 else 2.0 ** -22) * gscale
+                    check_bound(f"grid V n={m}", V, hq[:m], A0[:m], tol, floor)
+                    check_bound(f"grid dV n={m}", dV, dhq[:, :m], A[:, :m], 10 * tol,
+                                floor * max(1.0, max(1.0 / h for h in dx)))
+                if full is None:
+                    full = abp.bias_eval(ctx, to_dev(qq), mode=abp.ABP_EVAL_GRID, prec=prec)
+                    abp.abp_sync(ctx)
+                    full = tuple(t.cpu().numpy() for t in full)
+                assert np.array_equal(V, full[0][:m]) and np.array_equal(dV, full[1][:, :m]), (qdt, prec, m)
+            # one query alone, from the middle of a group of four
+            V1, dV1 = abp.bias_eval(ctx, to_dev(qq[:, 42:43].copy()), mode=abp.ABP_EVAL_GRID, prec=prec)
+            abp.abp_sync(ctx)
+            assert V1.cpu().numpy()[0] == full[0][42] and np.array_equal(dV1.cpu().numpy()[:, 0], full[1][:, 42])
