@@ -229,3 +229,41 @@ def test_grid_eval_ragged_batches_and_cell_edges(periodic, grid_n):
             V1, dV1 = abp.bias_eval(ctx, to_dev(qq[:, 42:43].copy()), mode=abp.ABP_EVAL_GRID, prec=prec)
             abp.abp_sync(ctx)
             assert V1.cpu().numpy()[0] == full[0][42] and np.array_equal(dV1.cpu().numpy()[:, 0], full[1][:, 42])
+
+
+@pytest.mark.parametrize("ndim,kernel,quantize", [(2, W.KERNEL_COMPACT, 0), (2, W.KERNEL_COMPACT, 1),
+                                                  (3, W.KERNEL_COMPACT, 0), (2, W.KERNEL_GAUSS, 0)])
+def test_mirror_catches_up_over_several_deposits(ndim, kernel, quantize):
+    """The FP32 mirror follows every deposit: after groups of deposits (single
+    hills and small batches; compact hills whose refresh rewrites only the
+    tiles they reach, and Gaussian hills on the matrix cores, refreshed
+    whole) with FP64 evaluations between some of them, FP32 and FP64 grid
+    evaluations agree everywhere, and the node arrays match the oracle's
+    grid."""
+    import dataclasses
+    from paper_1609_09833_amd import abp
+    device()
+    periodic = (1,) + (0,) * (ndim - 1)
+    grid_n = (150, 100) if ndim == 2 else (70, 40, 6)
+    spec = dataclasses.replace(_spec(ndim, periodic, grid_n, kernel=kernel), quantize=quantize)
+    hills = _hills(spec, 30, 131 + ndim + kernel)
+    ctx = abp.Context(spec, capacity=hills.n)
+    rng = np.random.default_rng(11)
+    qd = to_dev(np.vstack([rng.uniform(spec.lo[i], spec.hi[i], 4096) for i in range(ndim)]))
+    k = 0
+    for group in ((1, 2, 1), (3,), (1, 1, 1, 1), (5, 2), (1,), (4, 3, 4)):
+        for m in group:
+            abp.bias_deposit(ctx, to_dev(hills.centers[:, k:k + m]), to_dev(hills.heights[k:k + m]))
+            k += m
+            if m == 2:                   # FP64 evaluations between deposits
+                abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP64)
+        V64, dV64 = abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP64)
+        V32, dV32 = abp.bias_eval(ctx, qd, mode=abp.ABP_EVAL_GRID, prec=abp.ABP_PREC_FP32_KAHAN)
+        abp.abp_sync(ctx)
+        V64, dV64, V32, dV32 = (t.cpu().numpy() for t in (V64, dV64, V32, dV32))
+        scale = max(np.abs(V64).max(), 1e-30)
+        assert np.abs(V32 - V64).max() <= 1e-5 * scale, (k, np.abs(V32 - V64).max(), scale)
+        gscale = max(np.abs(dV64).max(), 1e-30)
+        assert np.abs(dV32 - dV64).max() <= 1e-4 * gscale, (k, np.abs(dV32 - dV64).max(), gscale)
+    assert k == hills.n
+    _check(spec, abp.abp_grid_export(ctx), hills)
