@@ -18,12 +18,15 @@
 // misses the tile is skipped, which is the Nbase^d saving of eq. Cupdate at
 // tile granularity.
 //
-// Evaluation: one thread per query, 2^ndim corners x 2^ndim arrays gathered
-// from the FP64 node-interleaved layout in FP64 arithmetic, or from the FP32
-// mirror the host layer refreshes after every deposit in FP32 arithmetic:
-// cell-major for 1-D and 2-D grids (each cell holds its corners' entries, so
-// a query gathers one 16- or 64-byte record, one cache line, instead of one
-// line per corner), node-major for 3-D.
+// Evaluation: 2^ndim corners x 2^ndim arrays gathered from the FP64
+// node-interleaved layout in FP64 arithmetic, or from the FP32 mirror the
+// host layer refreshes after every deposit in FP32 arithmetic: cell-major for
+// 1-D and 2-D grids (each cell holds its corners' entries, so a query gathers
+// one 16- or 64-byte record, one cache line, instead of one line per corner),
+// node-major for 3-D. In 2-D a group of four lanes fetches each of its four
+// queries' data together, 16 bytes a lane, and passes it through LDS to the
+// query's lane (k_grid_eval_cells32, k_grid_eval_nodes64); otherwise one
+// thread gathers for each query (k_grid_eval).
 #include <algorithm>
 
 #include "abp_device.h"
